@@ -1,0 +1,620 @@
+"""Plan compiler: spin-free terms -> a list of tensor operations for the HIP runtime.
+
+Build-time tool.  Input: the spin-free terms of E_corr, R1 and S2 from
+algebra.derive().  Output: a text plan (one operation per line) that the C++
+runtime parses at set-up and executes with the library's kernels.
+
+Tensors and their axis ranges (C core, A active, V virtual, H = C+A, P = A+V,
+G = all orbitals, X = auxiliary DF index):
+  inputs   f(G,G)  B(X,G,G)  T1(H,P)  T2(H,H,P,P)
+  prepared gA(A,A) = Gamma1/2, eA(A,A) = 1 - Gamma1/2, K2(A^4), K3(A^6),
+           I4(H,H,H,H) I3(H,H,H,P) IJ(H,H,P,P) IK(H,P,H,P): (pr|qs) blocks with at
+           most two particle indices, built once from B
+  outputs  R1(H,P)  R2(H,H,P,P)  E (scalar)
+Two-electron integrals with three or four particle indices are never formed:
+they are contracted through B.  The terms of the particle-particle ladder
+sum_{ef} (ce|df) Y[k,l,e,f] are collected into one tau(H,H,P,P) and applied by
+the LADDER operation, which builds (ce|df) from B in chunks.
+
+Every other term is factorized greedily into binary contractions; terms whose
+last contraction pairs the same stored tensor with the same index pattern share
+one accumulated intermediate ("sum before contract").
+"""
+from __future__ import annotations
+
+import itertools
+from collections import OrderedDict
+from fractions import Fraction
+
+from .algebra import A, C, G, H, P, V, RANGE_NAME, SFTerm
+
+X = 8          # auxiliary range mask (not an orbital space)
+RN = dict(RANGE_NAME)
+RN[X] = "X"
+SMALL = (C, A, H)
+BIG = (V, P, G)
+
+# representative sizes for the cost model (the 809-orbital CAS(12,12) shape)
+COST_SIZES = {"nc": 40, "na": 12, "nv": 757, "naux": 2200}
+
+
+def extent(r, sz=COST_SIZES):
+    nc, na, nv, nx = sz["nc"], sz["na"], sz["nv"], sz["naux"]
+    return {C: nc, A: na, V: nv, H: nc + na, P: na + nv, G: nc + na + nv, X: nx}[r]
+
+
+# declared axis ranges of stored tensors
+DECL = {
+    "f": (G, G), "B": (X, G, G), "T1": (H, P), "T2": (H, H, P, P),
+    "gA": (A, A), "eA": (A, A), "K2": (A,) * 4, "K3": (A,) * 6,
+    "I4": (H, H, H, H), "I3": (H, H, H, P), "IJ": (H, H, P, P), "IK": (H, P, H, P),
+    "R1": (H, P), "R2": (H, H, P, P), "TAU": (H, H, P, P),
+}
+
+
+def parent(r):
+    return H if r in SMALL else P
+
+
+class Operand:
+    __slots__ = ("name", "ranges", "labels", "src")
+
+    def __init__(self, name, ranges, labels):
+        self.name = name
+        self.ranges = tuple(ranges)
+        self.labels = tuple(labels)
+        self.src = None
+
+    def size(self):
+        n = 1
+        for r in self.ranges:
+            n *= extent(r)
+        return n
+
+    def text(self):
+        return f"{self.name}:{''.join(RN[r] for r in self.ranges)}:{','.join(str(l) for l in self.labels)}"
+
+
+def _eri_operand(labels, rng):
+    """(pr|qs) factor with labels (p,r,q,s) -> stored block operand, or None if it must use B."""
+    p, r, q, s = labels
+    par = [parent(rng[x]) for x in labels]
+    nbig = sum(1 for x in par if x == P)
+    if nbig > 2:
+        return None
+    # canonical blocks: I4 (HH|HH), I3 (HH|HP), IJ (HH|PP), IK (HP|HP)
+    cands = []
+    perms = [(0, 1, 2, 3), (1, 0, 2, 3), (0, 1, 3, 2), (1, 0, 3, 2),
+             (2, 3, 0, 1), (3, 2, 0, 1), (2, 3, 1, 0), (3, 2, 1, 0)]
+    table = {(H, H, H, H): "I4", (H, H, H, P): "I3", (H, H, P, P): "IJ", (H, P, H, P): "IK"}
+    for pm in perms:
+        pp = tuple(par[i] for i in pm)
+        if pp in table:
+            ls = tuple(labels[i] for i in pm)
+            cands.append(Operand(table[pp], [rng[x] for x in ls], ls))
+    return cands[0]
+
+
+class Plan:
+    def __init__(self):
+        self.lines = []
+        self.tmp = 0
+        self.flops = 0.0
+        self.ladder_flops = 0.0
+
+    def new_tmp(self, ranges):
+        name = f"t{self.tmp}"
+        self.tmp += 1
+        self.lines.append(f"ALLOC {name} {''.join(RN[r] for r in ranges)}")
+        return name
+
+    def free(self, name):
+        self.lines.append(f"FREE {name}")
+
+    def contract(self, out: Operand, alpha, a: Operand, b: Operand, fresh=False):
+        labs = set(a.labels) | set(b.labels)
+        rng = {}
+        for o in (a, b, out):
+            for l, r in zip(o.labels, o.ranges):
+                rng[l] = r
+        fl = 2.0
+        for l in labs:
+            fl *= extent(rng[l])
+        self.flops += fl
+        kind = "CONTRACT0" if fresh else "CONTRACT"
+        self.lines.append(f"{kind} {_num(alpha)} {out.text()} {a.text()} {b.text()}")
+
+    def add(self, out: Operand, alpha, a: Operand):
+        self.lines.append(f"ADD {_num(alpha)} {out.text()} {a.text()}")
+
+
+def _num(x):
+    x = Fraction(x)
+    return f"{x.numerator}/{x.denominator}"
+
+
+def factor_operands(t: SFTerm):
+    """Operands of a spin-free term after choosing integral blocks / DF factors."""
+    ops = []
+    aux = 0
+    for name, ls in t.factors:
+        if name == "eri":
+            o = _eri_operand(ls, t.rng)
+            if o is not None:
+                ops.append(o)
+            else:
+                p, r, q, s = ls
+                xl = f"X{aux}"
+                aux += 1
+                ops.append(Operand("B", (X, t.rng[p], t.rng[r]), (xl, p, r)))
+                ops.append(Operand("B", (X, t.rng[q], t.rng[s]), (xl, q, s)))
+        else:
+            ops.append(Operand(name, [t.rng[l] for l in ls], ls))
+    return ops
+
+
+def _rng_of(ops, out_labels=(), out_ranges=()):
+    r = {}
+    for o in ops:
+        for l, x in zip(o.labels, o.ranges):
+            r[l] = x
+    for l, x in zip(out_labels, out_ranges):
+        r[l] = x
+    return r
+
+
+def _pair_cost(a, b, keep, rng):
+    labs = set(a.labels) | set(b.labels)
+    fl = 1.0
+    for l in labs:
+        fl *= extent(rng[l])
+    for o in (a, b):
+        if o.name == "ERI":           # the integral block is built from its DF factors
+            fb = extent(X)
+            for l in o.labels:
+                fb *= extent(rng[l])
+            fl += fb
+    outl = [l for l in labs if l in keep]
+    sz = 1.0
+    for l in outl:
+        sz *= extent(rng[l])
+    return fl, sz, outl
+
+
+def greedy_tree(ops, ext, rng, cap=2.5e9):
+    """Cheapest binary contraction tree (exhaustive for up to 6 operands, greedy beyond).
+
+    Returns (steps, flops, result operand); steps are (a, b, new) in execution order.
+    Intermediates larger than `cap` elements are avoided when possible.
+    """
+    ops = list(ops)
+    if len(ops) <= 6:
+        best = _search(tuple(ops), frozenset(ext), rng, cap, {})
+        return list(best[2]), best[1], best[3]
+    steps = []
+    total = 0.0
+    while len(ops) > 1:
+        best = None
+        for i, j in itertools.combinations(range(len(ops)), 2):
+            others = set(ext)
+            for k, o in enumerate(ops):
+                if k not in (i, j):
+                    others |= set(o.labels)
+            fl, sz, outl = _pair_cost(ops[i], ops[j], others, rng)
+            shared = set(ops[i].labels) & set(ops[j].labels)
+            pen = 0 if shared else 1
+            key = (pen, sz > cap, fl, sz)
+            if best is None or key < best[0]:
+                best = (key, i, j, outl)
+        _, i, j, outl = best
+        total += best[0][2]
+        new = _new_operand(ops[i], ops[j], outl, rng)
+        steps.append((ops[i], ops[j], new))
+        ops = [o for k, o in enumerate(ops) if k not in (i, j)] + [new]
+    return steps, total, ops[0]
+
+
+def _new_operand(a, b, outl, rng):
+    outl = sorted(outl, key=lambda l: (l not in a.labels,
+                                       a.labels.index(l) if l in a.labels else b.labels.index(l)))
+    return Operand("?", [rng[l] for l in outl], outl)
+
+
+def _search(ops, ext, rng, cap, memo):
+    """(penalty, flops, steps, result) of the cheapest tree over the operand tuple."""
+    if len(ops) == 1:
+        return (0, 0.0, (), ops[0])
+    best = None
+    n = len(ops)
+    for i, j in itertools.combinations(range(n), 2):
+        others = set(ext)
+        for k, o in enumerate(ops):
+            if k not in (i, j):
+                others |= set(o.labels)
+        fl, sz, outl = _pair_cost(ops[i], ops[j], others, rng)
+        shared = set(ops[i].labels) & set(ops[j].labels)
+        pen = (0 if shared else 1) + (1 if sz > cap else 0)
+        new = _new_operand(ops[i], ops[j], outl, rng)
+        rest = tuple(o for k, o in enumerate(ops) if k not in (i, j)) + (new,)
+        sub = _search(rest, ext, rng, cap, memo)
+        cand = (pen + sub[0], 2.0 * fl + sub[1], ((ops[i], ops[j], new),) + sub[2], sub[3])
+        if best is None or cand[:2] < best[:2]:
+            best = cand
+    return best
+
+
+def _is_ladder(ops, ext, rng):
+    """B(X,c,e) B(X,d,f) with c,d,e,f particle-type, c,d = ext[2],ext[3], e,f internal."""
+    bs = [o for o in ops if o.name == "B"]
+    if len(bs) != 2 or len(ext) != 4:
+        return None
+    b1, b2 = bs
+    if b1.labels[0] != b2.labels[0]:
+        return None
+    if any(parent(r) != P for r in b1.ranges[1:] + b2.ranges[1:]):
+        return None
+    k, l, c, d = ext
+    for x, y in ((b1, b2), (b2, b1)):
+        if c in x.labels[1:] and d in y.labels[1:]:
+            e = x.labels[1] if x.labels[2] == c else x.labels[2]
+            f = y.labels[1] if y.labels[2] == d else y.labels[2]
+            if e in ext or f in ext or e == c or f == d:
+                return None
+            if rng[c] != P or rng[d] != P:
+                return None
+            rest = [o for o in ops if o is not b1 and o is not b2]
+            labs = set()
+            for o in rest:
+                labs |= set(o.labels)
+            if labs != {k, l, e, f}:
+                return None
+            return rest, (k, l, e, f)
+    return None
+
+
+def compile_plan(e_terms, r1_terms, s2_terms):
+    plan = Plan()
+    groups = OrderedDict()     # key -> list of (coef, term ops...)
+    ladder = []
+    direct = []
+
+    dfgroups = OrderedDict()
+    dfterms = []
+
+    def handle(t: SFTerm, target, out_ranges):
+        ops = factor_operands(t)
+        rng = _rng_of(ops, t.ext, out_ranges)
+        ext = t.ext
+        if target == "R2":
+            lad = _is_ladder(ops, ext, rng)
+            if lad is not None:
+                ladder.append((t.coef, lad[0], lad[1], rng))
+                return
+        bs = [o for o in ops if o.name == "B"]
+        if bs:
+            dfterms.append((target, t.coef, ext, out_ranges, ops, rng))
+            return
+        if len(ops) == 1:
+            direct.append((target, t.coef, ext, out_ranges, ops, rng))
+            return
+        # sum-before-contract: the last contraction pairs one stored operand P0 with an
+        # intermediate Y of the others; pick the P0 with the cheapest total, preferring T2
+        _, gflops, _ = greedy_tree(ops, ext, rng)
+        choice = None
+        for big in range(len(ops)):
+            if ops[big].size() < 1e6:
+                continue
+            rest = [o for i, o in enumerate(ops) if i != big]
+            keep = set(ext) | set(ops[big].labels)
+            if len(rest) == 1:
+                ys, yf, Yo = [], 0.0, rest[0]
+            else:
+                ys, yf, Yo = greedy_tree(rest, keep, rng)
+            fl_last, _, _ = _pair_cost(ops[big], Yo, set(ext), rng)
+            cost = yf + 2.0 * fl_last
+            pref = 0 if ops[big].name == "T2" else 1
+            cand = (cost > 1.5 * gflops + 1e6, pref, cost)
+            if choice is None or cand < choice[0]:
+                choice = (cand, big, ys, yf, Yo)
+        if choice is not None and not choice[0][0]:
+            _, big, ysteps, yflops, Yop = choice
+            P0 = ops[big]
+            ren = {}
+            for i, l in enumerate(ext):
+                ren[l] = f"o{i}"
+            cnt = 0
+            for l in P0.labels:
+                if l not in ren:
+                    ren[l] = f"c{cnt}"
+                    cnt += 1
+            ylabs = sorted(Yop.labels, key=lambda l: ren[l])
+            key = (target, P0.name, P0.ranges, tuple(ren[l] for l in P0.labels),
+                   tuple(out_ranges), tuple((ren[l], rng[l]) for l in ylabs))
+            groups.setdefault(key, []).append((t.coef, ysteps, Yop, ylabs, P0, ext, out_ranges, rng, ren))
+        else:
+            direct.append((target, t.coef, ext, out_ranges, ops, rng))
+
+    for t in r1_terms:
+        handle(t, "R1", (t.rng[t.ext[0]], t.rng[t.ext[1]]))
+    for t in s2_terms:
+        handle(t, "R2", tuple(t.rng[l] for l in t.ext))
+    res_lines_start = len(plan.lines)
+    plan.lines.append("SECTION residual")
+    plan.lines.append("ZERO R1")
+    plan.lines.append("ZERO R2")
+    _emit_groups(plan, groups)
+    _emit_df_terms(plan, dfterms)
+    _emit_direct(plan, direct)
+    plan.lines.append("SYMMETRIZE R2")
+    # ladder: tau accumulated, symmetrized over pairs, contracted with (ce|df) from B
+    if ladder:
+        plan.lines.append("ALLOC TAU HHPP")
+        plan.lines.append("ZERO TAU")
+        for coef, rest, (k, l, e, f), rng in ladder:
+            out = Operand("TAU", (rng[k], rng[l], rng[e], rng[f]), (k, l, e, f))
+            _emit_into(plan, coef, rest, out, rng)
+        plan.lines.append("SYMMETRIZE TAU")
+        plan.lines.append("LADDER R2 TAU")
+        nP, nH, nx = extent(P), extent(H), extent(X)
+        plan.ladder_flops = nP * nP * (nP + 1) / 2 * nP * nx * 2 + nH * nH * nP * (nP + 1) / 2 * nP * nP * 2
+        plan.flops += plan.ladder_flops
+        plan.lines.append("FREE TAU")
+    plan.lines.append("MASK R1 R2")
+    plan.lines.append("END")
+    res_flops = plan.flops
+    # energy: every term is a full contraction
+    plan.lines.append("SECTION energy")
+    plan.lines.append("ZERO E")
+    groups.clear()
+    dfterms.clear()
+    direct.clear()
+    for t in e_terms:
+        handle(t, "E", ())
+    _emit_groups(plan, groups)
+    _emit_df_terms(plan, dfterms)
+    _emit_direct(plan, direct)
+    plan.lines.append("END")
+    return plan, res_flops
+
+
+def _emit_steps(plan, steps, final_out=None, alpha=1):
+    """Emit contractions of a tree; the last one goes into final_out (accumulate) if given.
+
+    Returns the mapping id(tree node) -> emitted operand for intermediates kept alive
+    (only when final_out is None: the caller frees them).
+    """
+    names = {}
+    for idx, (a, b, new) in enumerate(steps):
+        a = names.get(id(a), a)
+        b = names.get(id(b), b)
+        last = idx == len(steps) - 1
+        if last and final_out is not None:
+            _emit_pair(plan, final_out, alpha, a, b, fresh=False)
+        else:
+            nm = plan.new_tmp(new.ranges)
+            o = Operand(nm, new.ranges, new.labels)
+            _emit_pair(plan, o, 1, a, b, fresh=True)
+            names[id(new)] = o
+        for x in (a, b):
+            if x.name.startswith("t") and x.name[1:].isdigit():
+                plan.free(x.name)
+    return names
+
+
+def _emit_pair(plan, out, alpha, a, b, fresh):
+    if a.name == "ERI" or b.name == "ERI":
+        eri, y = (a, b) if a.name == "ERI" else (b, a)
+        rng = {}
+        for o in (out, eri, y):
+            for l, r in zip(o.labels, o.ranges):
+                rng[l] = r
+        if fresh:
+            plan.lines.append(f"ZERO {out.name}")
+        _emit_dfc(plan, alpha, out, eri.src[0], eri.src[1], eri.labels, y, rng)
+    else:
+        plan.contract(out, alpha, a, b, fresh=fresh)
+
+
+def _emit_into(plan, coef, ops, out, rng):
+    if len(ops) == 1:
+        plan.add(out, coef, ops[0])
+        return
+    steps, _, _ = greedy_tree(ops, set(out.labels), rng)
+    _emit_steps(plan, steps, final_out=out, alpha=coef)
+
+
+def _emit_groups(plan, groups):
+    for key, members in groups.items():
+        target = key[0]
+        coef0, ysteps0, Yop0, ylabs0, P0, ext0, out_ranges0, rng0, ren0 = members[0]
+        if len(members) == 1 and not ysteps0:
+            # plain product of two stored tensors
+            out = Operand(target, out_ranges0, ext0)
+            plan.contract(out, coef0, P0, Yop0)
+            continue
+        yr = [rng0[l] for l in ylabs0]
+        acc = plan.new_tmp(yr)
+        plan.lines.append(f"ZERO {acc}")
+        for coef, ysteps, Yop, ylabs, P0m, ext, out_ranges, rng, ren in members:
+            accop = Operand(acc, [rng[l] for l in ylabs], ylabs)
+            if not ysteps:
+                plan.add(accop, coef, Yop)
+            else:
+                _emit_steps(plan, ysteps, final_out=accop, alpha=coef)
+        out = Operand(target, out_ranges0, ext0)
+        plan.contract(out, 1, P0, Operand(acc, yr, ylabs0))
+        plan.free(acc)
+
+
+def _nbig(o):
+    return sum(1 for r in o.ranges if r != X and parent(r) == P)
+
+
+def _emit_df_terms(plan, dfterms):
+    """Terms whose integral has three or more particle indices.
+
+    1. A two-index factor (T1, gA, eA, f) that shares a particle index with one B
+       factor and no index with the other is contracted into it first when that
+       lowers the number of particle indices ("dressing").
+    2. The integral (pr|qs) = sum_X L1[X,p,r] L2[X,q,s] then enters the tree
+       search as one leaf: whichever operand it meets is contracted with it by a
+       DFC operation that builds the integral block by block from L1, L2.
+    Terms whose last step contracts the same integral pattern with the same
+    intermediate pattern share one accumulated intermediate.
+    """
+    groups = OrderedDict()
+    for target, coef, ext, out_ranges, ops, rng in dfterms:
+        bs = [o for o in ops if o.name == "B"]
+        rest = [o for o in ops if o.name != "B"]
+        pre = []          # dressing steps (a, b, new)
+        changed = True
+        while changed:
+            changed = False
+            for i, b in enumerate(bs):
+                other = bs[1 - i]
+                for f in rest:
+                    if len(f.labels) != 2:
+                        continue
+                    sh = set(f.labels) & set(b.labels[1:])
+                    if not sh or set(f.labels) & set(other.labels[1:]):
+                        continue
+                    if any(set(f.labels) & set(g.labels) for g in rest if g is not f):
+                        # the free index of f must stay outside the remaining factors
+                        free = set(f.labels) - sh
+                        if free & set().union(*[set(g.labels) for g in rest if g is not f]):
+                            continue
+                    outl = [b.labels[0]] + [l for l in b.labels[1:] if l not in sh] + \
+                           [l for l in f.labels if l not in sh]
+                    if len(outl) != 3:
+                        continue
+                    new = Operand("?", [rng[l] for l in outl], outl)
+                    if _nbig(new) >= _nbig(b):
+                        continue
+                    pre.append((b, f, new))
+                    bs[i] = new
+                    rest = [g for g in rest if g is not f]
+                    changed = True
+                    break
+                if changed:
+                    break
+        l1, l2 = bs
+        if _nbig(l1) + _nbig(l2) <= 2:
+            # small enough to form: ordinary tree over all operands
+            allops = [l1, l2] + rest
+            if len(allops) == 1:
+                continue
+            steps, _, _ = greedy_tree(allops, set(ext), rng)
+            out = Operand(target, out_ranges, ext)
+            names = _emit_steps(plan, pre, final_out=None) if pre else {}
+            steps = [(names.get(id(a), a), names.get(id(b), b), n) for a, b, n in steps]
+            _emit_steps(plan, steps, final_out=out, alpha=coef)
+            continue
+        eri_l = l1.labels[1:] + l2.labels[1:]
+        eri = Operand("ERI", [rng[l] for l in eri_l], eri_l)
+        eri.src = (l1, l2)
+        steps, _, res = greedy_tree([eri] + rest, set(ext), rng)
+        last_a, last_b, _ = steps[-1]
+        if last_a is eri or last_b is eri:
+            Yfinal = last_b if last_a is eri else last_a
+            ysteps = steps[:-1]
+            ren = {l: f"o{i}" for i, l in enumerate(ext)}
+            cnt = 0
+            for l in eri_l:
+                if l not in ren:
+                    ren[l] = f"c{cnt}"
+                    cnt += 1
+            ylabs = sorted(Yfinal.labels, key=lambda l: ren.get(l, "z"))
+            key = (target, tuple(ren[l] for l in eri_l), tuple(rng[l] for l in eri_l),
+                   tuple(out_ranges), tuple((ren.get(l), rng[l]) for l in ylabs),
+                   tuple(_src_key(x, ren) for x in (l1, l2)))
+            groups.setdefault(key, []).append((coef, pre, ysteps, Yfinal, ylabs, eri, ext, out_ranges, rng))
+        else:
+            names = _emit_steps(plan, pre, final_out=None) if pre else {}
+            steps = [(names.get(id(a), a), names.get(id(b), b), n) for a, b, n in steps]
+            out = Operand(target, out_ranges, ext)
+            _emit_steps(plan, steps, final_out=out, alpha=coef)
+    for key, members in groups.items():
+        target = key[0]
+        coef0, pre0, ysteps0, Y0, ylabs0, eri0, ext0, out_ranges0, rng0 = members[0]
+        yr = [rng0[l] for l in ylabs0]
+        acc = plan.new_tmp(yr)
+        plan.lines.append(f"ZERO {acc}")
+        for coef, pre, ysteps, Yf, ylabs, eri, ext, out_ranges, rng in members:
+            accop = Operand(acc, [rng[l] for l in ylabs], ylabs)
+            names = _emit_steps(plan, pre, final_out=None) if pre else {}
+            if not ysteps:
+                plan.add(accop, coef, names.get(id(Yf), Yf))
+            else:
+                ys = [(names.get(id(a), a), names.get(id(b), b), n) for a, b, n in ysteps]
+                _emit_steps(plan, ys, final_out=accop, alpha=coef)
+            for nm in names.values():
+                pass
+        # the (possibly dressed) DF factors of the first member define the integral
+        names0 = {}
+        l1, l2 = eri0.src
+        out = Operand(target, out_ranges0, ext0)
+        if pre0:
+            names0 = _emit_steps(plan, pre0, final_out=None)
+        l1 = names0.get(id(l1), l1)
+        l2 = names0.get(id(l2), l2)
+        _emit_dfc(plan, 1, out, l1, l2, eri0.labels, Operand(acc, yr, ylabs0), rng0)
+        plan.free(acc)
+        for o in (l1, l2):
+            if o.name.startswith("t") and o.name[1:].isdigit():
+                plan.free(o.name)
+
+
+def _src_key(o, ren):
+    return (o.name, o.ranges, tuple(ren.get(l, "x") for l in o.labels[1:]))
+
+
+def _emit_dfc(plan, alpha, out, l1, l2, eri_labels, y, rng):
+    labs = set(out.labels) | set(eri_labels) | set(y.labels)
+    fl = 2.0
+    for l in labs:
+        fl *= extent(rng[l])
+    fb = 2.0 * extent(X)
+    for l in eri_labels:
+        fb *= extent(rng[l])
+    plan.flops += fl + fb
+    plan.lines.append(f"DFC {_num(alpha)} {out.text()} {l1.text()} {l2.text()} {y.text()}")
+
+
+def _emit_dfgroups(plan, dfgroups):
+    for key, members in dfgroups.items():
+        target = key[0]
+        coef0, ysteps0, Yop0, ylabs0, eri0, ext0, out_ranges0, rng0 = members[0]
+        yr = [rng0[l] for l in ylabs0]
+        acc = plan.new_tmp(yr)
+        plan.lines.append(f"ZERO {acc}")
+        for coef, ysteps, Yop, ylabs, eri_l, ext, out_ranges, rng in members:
+            accop = Operand(acc, [rng[l] for l in ylabs], ylabs)
+            if not ysteps:
+                plan.add(accop, coef, Yop)
+            else:
+                _emit_steps(plan, ysteps, final_out=accop, alpha=coef)
+        out = Operand(target, out_ranges0, ext0)
+        eri = Operand("ERI", [rng0[l] for l in eri0], eri0)
+        labs = set(ext0) | set(eri0) | set(ylabs0)
+        fl = 2.0
+        for l in labs:
+            fl *= extent(rng0[l])
+        # building (pr|qs) from B: 2 * naux * prod(eri extents)
+        fb = 2.0 * extent(X)
+        for l in eri0:
+            fb *= extent(rng0[l])
+        plan.flops += fl + fb
+        plan.lines.append(f"DFC 1/1 {out.text()} {eri.text()} {Operand(acc, yr, ylabs0).text()}")
+        plan.free(acc)
+
+
+def _emit_direct(plan, direct):
+    for target, coef, ext, out_ranges, ops, rng in direct:
+        out = Operand(target, out_ranges, ext)
+        _emit_into(plan, coef, ops, out, rng)
+
+
+def _emit_scalar(plan, coef, ops, rng):
+    steps, _, _ = greedy_tree(ops, set(), rng)
+    out = Operand("E", (), ())
+    _emit_steps(plan, steps, final_out=out, alpha=coef)
