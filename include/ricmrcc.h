@@ -1,0 +1,122 @@
+/*
+ * ricmrcc.h -- C ABI of the MI355X (gfx950) spin-free RIC-MRCCSD residual engine.
+ *
+ * The library evaluates, on one GPU, the hot path of one amplitude iteration of
+ * spin-free RIC-MRCCSD (Szenes et al., "Efficient Implementation of the
+ * Spin-Free Renormalized Internally-Contracted Multireference Coupled Cluster
+ * Theory"):
+ *   - the many-body residuals r^c_k = Hbar^c_k, r^{cd}_{kl} = Hbar^{cd}_{kl} and the
+ *     energy E = Hbar_0 of Hbar = H + [H,T] + 1/2[[H,T],T] (Section 2.2), with the
+ *     paper's approximations on the two-fold commutator (Section 2.2: energy terms
+ *     with two three-active amplitudes dropped; residual terms with two
+ *     active-carrying amplitudes or a two-body cumulant dropped),
+ *   - spin-free (Section 2.3): only the alpha (singles) and alpha-beta (doubles)
+ *     components are stored and computed,
+ *   - two-electron integrals from density fitting, (pq|rs) = sum_P B[P,p,q] B[P,r,s];
+ *     integrals with three or four virtual-type indices are never stored,
+ *   - the flow-regularized Jacobi update (Section 2.2, eq. ric-update).
+ *
+ * Orbital spaces (Table 1): core (nc), active (na), virtual (nv), ordered
+ * core, active, virtual; n = nc + na + nv.  Hole range H = core + active
+ * (nH = nc + na), particle range P = active + virtual (nP = na + nv).
+ *
+ * Amplitude / residual layout ("dense hole-particle layout", row-major, fp64):
+ *   T1[k][c]        k in H, c in P:           t^c_k (alpha spin)            nH*nP
+ *   T2[k][l][c][d]  k,l in H, c,d in P:       t^{c dbar}_{k lbar}           nH*nH*nP*nP
+ * with T2[k][l][c][d] == T2[l][k][d][c] (spin-free pair symmetry,
+ * eq. spinfree-perm-sym).  The excluded all-active blocks (T1 active->active,
+ * T2 with all four indices active; Section 2.2) are kept at zero: the library
+ * writes zeros there in R1/R2 and never changes them in T1/T2.  The eight
+ * doubles excitation classes of Section 3.2 (IJAB, IJTU, TUAB, ITAB, ITUV,
+ * IJTA, TUVA, ITUA with its two stored blocks) are sub-blocks of this layout.
+ *
+ * Pointers: every array argument is a DEVICE pointer on the context's device
+ * unless stated otherwise; scalar outputs documented as "host" are host
+ * pointers written after the context's stream has been synchronized.
+ * All work is enqueued on the stream given to ric_create (NULL = default
+ * stream).  A context is not thread-safe; calls that overlap on one context race.
+ *
+ * Errors: functions return RIC_OK (0) or a negative code; the message of the
+ * last error is available from ric_last_error().  No C++ exception crosses
+ * the ABI.  There is no CPU fallback: every step runs in the library's HIP kernels.
+ */
+#ifndef RICMRCC_H
+#define RICMRCC_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ric_ctx ric_ctx;
+
+enum {
+  RIC_OK = 0,
+  RIC_E_ARG = -1,       /* bad dimension, null pointer, bad option */
+  RIC_E_STATE = -2,     /* call before ric_set_spaces or before the required loads */
+  RIC_E_OOM = -3,       /* device allocation failed */
+  RIC_E_HIP = -4,       /* a HIP runtime call failed */
+  RIC_E_NONFINITE = -5, /* a residual, energy or norm is NaN/Inf */
+  RIC_E_PLAN = -6       /* the contraction plan file is missing or malformed */
+};
+
+enum { RIC_FP64 = 0, RIC_FP32MIX = 1 };
+
+/* Create a context on `device` using `hip_stream` (a hipStream_t, may be NULL).
+ * plan_path: the contraction plan generated from the paper's equations
+ * (plan.txt shipped next to the library); NULL selects that default file.
+ * Ownership: the context owns all device memory it allocates; release with ric_destroy. */
+int ric_create(ric_ctx** ctx, int device, void* hip_stream, const char* plan_path);
+void ric_destroy(ric_ctx* ctx);
+
+/* Orbital space sizes (Table 1).  nc, nv >= 0, 0 <= na <= 16, naux >= 1.
+ * Resets every loaded quantity. */
+int ric_set_spaces(ric_ctx* ctx, int nc, int na, int nv, int naux);
+
+/* Generalized Fock matrix f (Section 2.1), n x n row-major, symmetric; copied.
+ * Its diagonal gives the denominators Delta of eq. cc-update. */
+int ric_load_fock(ric_ctx* ctx, const double* f);
+
+/* Density-fitting factors B[P][p][q], naux x n x n row-major, symmetric in (p,q);
+ * copied.  Builds the stored integral blocks with at most two particle indices. */
+int ric_load_df(ric_ctx* ctx, const double* B);
+
+/* Spin-free RDMs of the active space (Section 2.3.2): G1[t][u] = Gamma^t_u,
+ * G2[t][u][v][w] = Gamma^{tu}_{vw}, G3[t][u][v][w][x][y] = Gamma^{tuv}_{wxy}
+ * (Gamma^{PQ..}_{RS..} = sum over column spins <a+_P a+_Q .. a_S a_R>); copied.
+ * Builds the spin-free two- and three-body cumulants.  May be NULL when na == 0. */
+int ric_load_rdms(ric_ctx* ctx, const double* G1, const double* G2, const double* G3);
+
+/* Many-body residuals (Section 2.2) of the amplitudes T1, T2 (layout above):
+ * R1 = r^c_k (alpha), R2 = r^{c dbar}_{k lbar}.  precision: RIC_FP64, or
+ * RIC_FP32MIX (large contractions with fp32 MFMA operands and fp64 accumulation;
+ * cumulant, energy and update work stays fp64).  R1, R2 are overwritten. */
+int ric_residual(ric_ctx* ctx, const double* T1, const double* T2, double* R1, double* R2, int precision);
+
+/* Flow-regularized Jacobi update (eq. ric-update), in place:
+ * t <- (t Delta + r) (1 - exp(-s Delta^2)) / Delta, Delta = sum of hole minus
+ * particle diagonal Fock elements; the factor is 0 at Delta = 0.
+ * step_norm2 (host): sum over stored amplitudes of (t_new - t)^2. */
+int ric_update(ric_ctx* ctx, double* T1, double* T2, const double* R1, const double* R2, double s,
+               double* step_norm2);
+
+/* Energy (Section 2.2): e_corr (host) = Hbar_0 - E0 with the energy approximation;
+ * e0 (host, may be NULL) = <Psi0|H|Psi0>, with h recovered from f (Section 2.1). */
+int ric_energy(ric_ctx* ctx, const double* T1, const double* T2, double* e_corr, double* e0);
+
+/* Particle-particle ladder alone (the dominant term of the residual):
+ * R2[k][l][c][d] += sum_{e,f in P} (ce|df) tau[k][l][e][f] with (ce|df) built from B
+ * block by block; tau must satisfy tau[k][l][e][f] == tau[l][k][f][e].
+ * For benchmarking and testing that contraction in isolation. */
+int ric_ladder(ric_ctx* ctx, const double* tau, double* R2, int precision);
+
+/* Milliseconds spent in the ladder during the last ric_residual/ric_ladder call,
+ * measured with HIP events on the context stream (host output). */
+int ric_last_timings(const ric_ctx* ctx, double* ladder_ms, double* total_ms);
+
+const char* ric_last_error(const ric_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RICMRCC_H */

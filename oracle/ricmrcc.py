@@ -327,6 +327,17 @@ class Evaluator:
         self._cache[key] = blk
         return blk
 
+    def antisym_eri(self, spaces):
+        """<pq||rs> = (pr|qs) - (ps|qr) over spin orbitals, for one block of spaces (cached)."""
+        key = ("v", spaces)
+        if key not in self._cache:
+            sp, sq, sr, ss = spaces
+            B = lambda a, b: self.block("B", (None, a, b))
+            v = np.einsum("Xpr,Xqs->pqrs", B(sp, sr), B(sq, ss), optimize=True)
+            v -= np.einsum("Xps,Xqr->pqrs", B(sp, ss), B(sq, sr), optimize=True)
+            self._cache[key] = v
+        return self._cache[key]
+
     def term(self, t: Term, out_labels, out_spaces):
         """Value of the term's coefficient tensor over out_labels (each restricted to out_spaces)."""
         space = dict(t.space)
@@ -342,17 +353,7 @@ class Evaluator:
                 letters[l] = next(pool)
             return letters[l]
 
-        variants = [[]]
-        for name, ls in t.factors:
-            if name == "v":                      # <pq||rs> = (pr|qs) - (ps|qr), density fitted
-                p, q, r, s = ls
-                new = []
-                for var in variants:
-                    new.append(var + [(1.0, [("B", ("X", p, r)), ("B", ("X", q, s))])])
-                    new.append(var + [(-1.0, [("B", ("X", p, s)), ("B", ("X", q, r))])])
-                variants = new
-            else:
-                variants = [var + [(1.0, [(name, ls)])] for var in variants]
+        variants = [[(1.0, [(name, ls)]) for name, ls in t.factors]]
         out = None
         for var in variants:
             coef = float(t.coef)
@@ -362,14 +363,11 @@ class Evaluator:
             for c, fl in var:
                 coef *= c
                 for name, ls in fl:
-                    if name == "B":
-                        aux_l = ("X", id(fl))
-                        sp_l = [space[x] for x in ls[1:]]
-                        ops.append(self.block("B", (None,) + tuple(sp_l)))
-                        subs.append(let(aux_l) + "".join(let(x) for x in ls[1:]))
+                    if name == "v":
+                        ops.append(self.antisym_eri(tuple(space[x] for x in ls)))
                     else:
                         ops.append(self.block(name, tuple(space[x] for x in ls)))
-                        subs.append("".join(let(x) for x in ls))
+                    subs.append("".join(let(x) for x in ls))
             spec = ",".join(subs) + "->" + "".join(let(l) for l in out_labels)
             val = coef * np.einsum(spec, *ops, optimize="greedy")
             out = val if out is None else out + val

@@ -1,0 +1,38 @@
+// Launchers of the bandwidth-bound kernels (kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace ric {
+
+constexpr int kMaxDims = 8;
+
+// Iteration space shared by an output view and an input view: element i of the
+// space (row-major over ext) is out[sum x_d so[d]] and in[sum x_d si[d]].
+struct Iter {
+  int nd = 0;
+  long total = 0;
+  long ext[kMaxDims] = {0};
+  long so[kMaxDims] = {0};
+  long si[kMaxDims] = {0};
+};
+
+hipError_t strided_copy(const Iter& it, double alpha, const double* in, double beta, double* out, hipStream_t st);
+hipError_t strided_copy_f32(const Iter& it, double alpha, const double* in, float* out, hipStream_t st);
+hipError_t fill(double* p, long n, double v, hipStream_t st);
+hipError_t symmetrize_pairs(double* x, int nh, int np, hipStream_t st);
+hipError_t mask_active(double* r1, double* r2, int nc, int na, int nv, hipStream_t st);
+// out[0] += alpha * sum a[i] b[i] (deterministic two-pass); partial needs 1024 doubles
+hipError_t dot_accumulate(const double* a, const double* b, long n, double alpha, double* out, double* partial,
+                          hipStream_t st);
+// regularized update of T1, T2 in place; norm2[0] = ||t_new - t||^2; partial needs 1024 doubles
+hipError_t ric_update_kernel(double* t1, double* t2, const double* r1, const double* r2, const double* eps, int nc,
+                             int na, int nv, double s, double* partial, double* norm2, hipStream_t st);
+hipError_t fock_diagonal(const double* f, int n, double* eps, hipStream_t st);
+hipError_t check_finite(const double* x, long n, int* flag, hipStream_t st);
+hipError_t prepare_cumulants(const double* g1, const double* g2, const double* g3, int na, double* ga, double* ea,
+                             double* l2, double* k2, double* l3, double* k3, hipStream_t st);
+hipError_t reference_energy(const double* f, int n, const double* I4, int nc, int na, const double* g1,
+                            const double* g2, double* out, hipStream_t st);
+hipError_t ladder_scatter_add(const double* C, int nh, int np, int c0, int c1, int ncol, double* r2, hipStream_t st);
+
+}  // namespace ric

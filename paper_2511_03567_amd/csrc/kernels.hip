@@ -1,0 +1,415 @@
+// Bandwidth-bound kernels of the residual engine (gfx950).
+//
+//  * strided copy/accumulate between tensor views (index permutation of the
+//    contraction operands, scatter-add of contraction results);
+//  * pair symmetrization X[k,l,c,d] + X[l,k,d,c] (eq. spinfree-perm-sym);
+//  * the flow-regularized Jacobi update with its step norm (eq. ric-update);
+//  * deterministic two-pass reductions (energy dot products, norms);
+//  * density-cumulant preparation (Section 2.1 and 2.3.2) and the reference energy.
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include "kernels.h"
+
+namespace ric {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kRedBlocks = 1024;
+
+inline int blocks_for(long n, int per = kThreads) {
+  long b = (n + per - 1) / per;
+  if (b > 1048576) b = 1048576;
+  return (int)(b < 1 ? 1 : b);
+}
+
+// ---- strided views ------------------------------------------------------------------
+
+// out[o(i)] = beta * out[o(i)] + alpha * in[s(i)] over the iteration space of `it`
+template <typename TO, typename TI>
+__global__ void __launch_bounds__(kThreads)
+strided_axpby(Iter it, double alpha, const TI* __restrict__ in, double beta, TO* __restrict__ out) {
+  const long total = it.total;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
+    long rem = t;
+    long so = 0, si = 0;
+#pragma unroll
+    for (int d = kMaxDims - 1; d >= 0; --d) {
+      if (d < it.nd) {
+        const long e = it.ext[d];
+        const long x = rem % e;
+        rem /= e;
+        so += x * it.so[d];
+        si += x * it.si[d];
+      }
+    }
+    const double v = alpha * (double)in[si];
+    out[so] = beta == 0.0 ? (TO)v : (TO)(beta * (double)out[so] + v);
+  }
+}
+
+__global__ void fill_kernel(double* __restrict__ p, long n, double v) {
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) p[t] = v;
+}
+
+// X[k,l,c,d] <- X[k,l,c,d] + X[l,k,d,c]; each pair handled by its lower index
+__global__ void symmetrize_kernel(double* __restrict__ x, int nh, int np) {
+  const long total = (long)nh * nh * np * np;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
+    const int d = (int)(t % np);
+    const int c = (int)((t / np) % np);
+    const int l = (int)((t / ((long)np * np)) % nh);
+    const int k = (int)(t / ((long)np * np * nh));
+    const long u = (((long)l * nh + k) * np + d) * np + c;
+    if (t < u) {
+      const double s = x[t] + x[u];
+      x[t] = s;
+      x[u] = s;
+    } else if (t == u) {
+      x[t] = 2.0 * x[t];
+    }
+  }
+}
+
+// zero the amplitude blocks whose indices are all active (Section 2.2)
+__global__ void mask_kernel(double* __restrict__ r1, double* __restrict__ r2, int nc, int na, int nh, int np) {
+  const long n2 = (long)na * na * na * na;
+  const long n1 = (long)na * na;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n2 + n1; t += (long)gridDim.x * blockDim.x) {
+    if (t < n2) {
+      const int d = (int)(t % na), c = (int)((t / na) % na);
+      const int l = (int)((t / n1) % na), k = (int)(t / (n1 * na));
+      r2[(((long)(nc + k) * nh + nc + l) * np + c) * np + d] = 0.0;
+    } else if (r1 != nullptr) {
+      const long s = t - n2;
+      const int c = (int)(s % na), k = (int)(s / na);
+      r1[(long)(nc + k) * np + c] = 0.0;
+    }
+  }
+}
+
+// ---- reductions ------------------------------------------------------------------------
+
+__device__ inline double block_sum(double v) {
+  __shared__ double sh[kThreads / 64];
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < kThreads / 64; ++i) s += sh[i];
+  }
+  __syncthreads();
+  return s;
+}
+
+// partial[b] = sum over the b-th contiguous share of a[i]*b[i]
+__global__ void __launch_bounds__(kThreads) dot_partial(const double* __restrict__ a, const double* __restrict__ b,
+                                                        long n, double* __restrict__ partial) {
+  const long per = (n + gridDim.x - 1) / gridDim.x;
+  const long beg = blockIdx.x * per;
+  const long end = beg + per < n ? beg + per : n;
+  double s = 0.0;
+  for (long i = beg + threadIdx.x; i < end; i += blockDim.x) s += a[i] * b[i];
+  s = block_sum(s);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// out[0] (+)= alpha * sum(partial[0..n))  in a fixed order
+__global__ void finish_sum(const double* __restrict__ partial, int n, double alpha, double* __restrict__ out,
+                           int accumulate) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s += partial[i];
+  s = block_sum(s);
+  if (threadIdx.x == 0) out[0] = accumulate ? out[0] + alpha * s : alpha * s;
+}
+
+// ---- regularized update -------------------------------------------------------------------
+
+__device__ inline double phi(double D, double s) {
+  // (1 - exp(-s D^2)) / D with the limit 0 at D = 0
+  if (D == 0.0) return 0.0;
+  return -expm1(-s * D * D) / D;
+}
+
+__global__ void __launch_bounds__(kThreads)
+update_kernel(double* __restrict__ t1, double* __restrict__ t2, const double* __restrict__ r1,
+              const double* __restrict__ r2, const double* __restrict__ eps, int nc, int na, int nv,
+              double s, double* __restrict__ partial) {
+  const int nh = nc + na, np = na + nv;
+  const long n1 = (long)nh * np;
+  const long n2 = (long)nh * nh * np * np;
+  const long total = n1 + n2;
+  const long per = (total + gridDim.x - 1) / gridDim.x;
+  const long beg = blockIdx.x * per;
+  const long end = beg + per < total ? beg + per : total;
+  double acc = 0.0;
+  for (long t = beg + threadIdx.x; t < end; t += blockDim.x) {
+    if (t < n1) {
+      const int k = (int)(t / np), c = (int)(t % np);
+      if (k >= nc && c < na) continue;
+      const double D = eps[k] - eps[nc + c];
+      const double nw = (t1[t] * D + r1[t]) * phi(D, s);
+      const double dv = nw - t1[t];
+      acc += dv * dv;
+      t1[t] = nw;
+    } else {
+      const long u = t - n1;
+      const int d = (int)(u % np);
+      const int c = (int)((u / np) % np);
+      const int l = (int)((u / ((long)np * np)) % nh);
+      const int k = (int)(u / ((long)np * np * nh));
+      if (k >= nc && l >= nc && c < na && d < na) continue;
+      const double D = eps[k] + eps[l] - eps[nc + c] - eps[nc + d];
+      const double nw = (t2[u] * D + r2[u]) * phi(D, s);
+      const double dv = nw - t2[u];
+      acc += dv * dv;
+      t2[u] = nw;
+    }
+  }
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
+__global__ void diag_kernel(const double* __restrict__ f, int n, double* __restrict__ eps) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) eps[i] = f[(long)i * n + i];
+}
+
+__global__ void nonfinite_kernel(const double* __restrict__ x, long n, int* __restrict__ flag) {
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x)
+    if (!isfinite(x[t])) flag[0] = 1;
+}
+
+// ---- density cumulants (Section 2.1, 2.3.2) ------------------------------------------------
+
+// gA = Gamma1 / 2 (per-spin 1-RDM), eA = 1 - Gamma1 / 2 (per-spin 1-hole RDM)
+__global__ void onebody_kernel(const double* __restrict__ g1, int na, double* __restrict__ ga, double* __restrict__ ea) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < na * na; t += gridDim.x * blockDim.x) {
+    const double h = 0.5 * g1[t];
+    ga[t] = h;
+    ea[t] = ((t / na) == (t % na) ? 1.0 : 0.0) - h;
+  }
+}
+
+// Lambda2[p,q,r,s] = G2 - G1[p,r] G1[q,s] + 1/2 G1[p,s] G1[q,r]
+__global__ void lambda2_kernel(const double* __restrict__ g1, const double* __restrict__ g2, int na,
+                               double* __restrict__ l2) {
+  const long n = (long)na * na * na * na;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
+    const int s = (int)(t % na), r = (int)((t / na) % na), q = (int)((t / ((long)na * na)) % na),
+              p = (int)(t / ((long)na * na * na));
+    l2[t] = g2[t] - g1[p * na + r] * g1[q * na + s] + 0.5 * g1[p * na + s] * g1[q * na + r];
+  }
+}
+
+// K2[p,q,r,s] = (2 Lambda2[p,q,r,s] + Lambda2[p,q,s,r]) / 6: kernel of the two-delta spin
+// expansion of the two-body cumulant
+__global__ void k2_kernel(const double* __restrict__ l2, int na, double* __restrict__ k2) {
+  const long n = (long)na * na * na * na;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
+    const int s = (int)(t % na), r = (int)((t / na) % na);
+    const long base = t - (long)r * na - s;
+    k2[t] = (2.0 * l2[t] + l2[base + (long)s * na + r]) / 6.0;
+  }
+}
+
+__device__ inline long ix6(int na, int a, int b, int c, int d, int e, int f) {
+  return ((((((long)a * na + b) * na + c) * na + d) * na + e) * na + f);
+}
+__device__ inline long ix4(int na, int a, int b, int c, int d) {
+  return ((((long)a * na + b) * na + c) * na + d);
+}
+
+// Lambda3 (spin-free three-body cumulant of a singlet) from Gamma3, Gamma1 and Lambda2
+__global__ void lambda3_kernel(const double* __restrict__ G, const double* __restrict__ L,
+                               const double* __restrict__ g3, int na, double* __restrict__ l3) {
+  const long n = (long)na * na * na * na * na * na;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
+    long r0 = t;
+    const int u = (int)(r0 % na); r0 /= na;
+    const int tt = (int)(r0 % na); r0 /= na;
+    const int s = (int)(r0 % na); r0 /= na;
+    const int r = (int)(r0 % na); r0 /= na;
+    const int q = (int)(r0 % na); r0 /= na;
+    const int p = (int)r0;
+#define G1(a, b) G[(a) * na + (b)]
+#define L2(a, b, c, d) L[ix4(na, a, b, c, d)]
+    double v = g3[t];
+    v -= G1(p, s) * L2(q, r, tt, u) + G1(q, tt) * L2(p, r, s, u) + G1(r, u) * L2(p, q, s, tt);
+    v += 0.5 * (G1(p, tt) * L2(q, r, s, u) + G1(p, u) * L2(q, r, tt, s) + G1(q, s) * L2(p, r, tt, u) +
+                G1(q, u) * L2(p, r, s, tt) + G1(r, s) * L2(p, q, u, tt) + G1(r, tt) * L2(p, q, s, u));
+    v -= G1(p, s) * G1(q, tt) * G1(r, u);
+    v += 0.5 * (G1(p, s) * G1(q, u) * G1(r, tt) + G1(p, tt) * G1(q, s) * G1(r, u) + G1(p, u) * G1(q, tt) * G1(r, s));
+    v -= 0.25 * (G1(p, tt) * G1(q, u) * G1(r, s) + G1(p, u) * G1(q, s) * G1(r, tt));
+#undef G1
+#undef L2
+    l3[t] = v;
+  }
+}
+
+// K3[pqr;stu] = sum_pi w_pi Lambda3[pqr; pi(stu)], w = 17/144 (identity), -1/144
+// (transpositions), -7/144 (three-cycles): kernel of the spin-delta expansion of lambda3
+__global__ void k3_kernel(const double* __restrict__ l3, int na, double* __restrict__ k3) {
+  const long n = (long)na * na * na * na * na * na;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
+    long r0 = t;
+    const int u = (int)(r0 % na); r0 /= na;
+    const int tt = (int)(r0 % na); r0 /= na;
+    const int s = (int)(r0 % na); r0 /= na;
+    const int r = (int)(r0 % na); r0 /= na;
+    const int q = (int)(r0 % na); r0 /= na;
+    const int p = (int)r0;
+    const double v = 17.0 * l3[t] - l3[ix6(na, p, q, r, tt, s, u)] - l3[ix6(na, p, q, r, u, tt, s)] -
+                     l3[ix6(na, p, q, r, s, u, tt)] - 7.0 * l3[ix6(na, p, q, r, tt, u, s)] -
+                     7.0 * l3[ix6(na, p, q, r, u, s, tt)];
+    k3[t] = v / 144.0;
+  }
+}
+
+// Reference energy from f, the (hh|hh) integral block and the active RDMs:
+// E0 = 2 sum_i f_ii + sum_tu f_tu G_tu - 2 sum_ij (ii|jj) + sum_ij (ij|ji)
+//      - 2 sum_i,tu (ii|tu) G_tu + sum_i,tu (iu|ti) G_tu - sum G_tu G_vw (tu|vw)
+//      + 1/2 sum G_tu G_vw (tw|vu) + 1/2 sum (tv|uw) G2[t,u,v,w]
+__global__ void e0_kernel(const double* __restrict__ f, int n, const double* __restrict__ I4, int nc, int na,
+                          const double* __restrict__ g1, const double* __restrict__ g2, double* __restrict__ out) {
+  const int nh = nc + na;
+  auto eri = [&](int p, int r, int q, int s) { return I4[(((long)p * nh + r) * nh + q) * nh + s]; };
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nc; i += blockDim.x) acc += 2.0 * f[(long)i * n + i];
+  for (int x = threadIdx.x; x < na * na; x += blockDim.x) {
+    const int t = x / na, u = x % na;
+    acc += f[(long)(nc + t) * n + nc + u] * g1[x];
+  }
+  for (int x = threadIdx.x; x < nc * nc; x += blockDim.x) {
+    const int i = x / nc, j = x % nc;
+    acc += -2.0 * eri(i, i, j, j) + eri(i, j, j, i);
+  }
+  for (long x = threadIdx.x; x < (long)nc * na * na; x += blockDim.x) {
+    const int i = (int)(x / (na * na)), t = (int)((x / na) % na), u = (int)(x % na);
+    const double g = g1[t * na + u];
+    acc += -2.0 * eri(i, i, nc + t, nc + u) * g + eri(i, nc + u, nc + t, i) * g;
+  }
+  const long na4 = (long)na * na * na * na;
+  for (long x = threadIdx.x; x < na4; x += blockDim.x) {
+    const int w = (int)(x % na), v = (int)((x / na) % na), u = (int)((x / ((long)na * na)) % na),
+              t = (int)(x / ((long)na * na * na));
+    const double gtu = g1[t * na + u], gvw = g1[v * na + w];
+    acc += -gtu * gvw * eri(nc + t, nc + u, nc + v, nc + w) + 0.5 * gtu * gvw * eri(nc + t, nc + w, nc + v, nc + u);
+    acc += 0.5 * eri(nc + t, nc + v, nc + u, nc + w) * g2[x];
+  }
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) out[0] = acc;
+}
+
+// ladder scatter: C[kl][(c - c0) * ncol + d] -> R2[k,l,c,d] and, for d < c, R2[l,k,d,c]
+__global__ void ladder_scatter(const double* __restrict__ Cm, int nh, int np, int c0, int c1, int ncol,
+                               double* __restrict__ r2) {
+  const long rows = (long)nh * nh;
+  const long cols = (long)(c1 - c0) * ncol;
+  const long total = rows * cols;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
+    const long kl = t / cols;
+    const long j = t % cols;
+    const int c = c0 + (int)(j / ncol);
+    const int d = (int)(j % ncol);
+    if (d > c) continue;
+    const int k = (int)(kl / nh), l = (int)(kl % nh);
+    if (d == c && k > l) continue;  // (l,k,c,c) is written from (k,l,c,c) so R2 stays exactly pair-symmetric
+    const double v = Cm[t];
+    r2[(((long)k * nh + l) * np + c) * np + d] += v;
+    if (d < c || k < l) r2[(((long)l * nh + k) * np + d) * np + c] += v;
+  }
+}
+
+}  // namespace
+
+// ---- launchers ------------------------------------------------------------------------------
+
+hipError_t strided_copy(const Iter& it, double alpha, const double* in, double beta, double* out, hipStream_t st) {
+  if (it.total <= 0) return hipSuccess;
+  hipLaunchKernelGGL((strided_axpby<double, double>), dim3(blocks_for(it.total)), dim3(kThreads), 0, st, it,
+                     alpha, in, beta, out);
+  return hipGetLastError();
+}
+
+hipError_t strided_copy_f32(const Iter& it, double alpha, const double* in, float* out, hipStream_t st) {
+  if (it.total <= 0) return hipSuccess;
+  hipLaunchKernelGGL((strided_axpby<float, double>), dim3(blocks_for(it.total)), dim3(kThreads), 0, st, it,
+                     alpha, in, 0.0, out);
+  return hipGetLastError();
+}
+
+hipError_t fill(double* p, long n, double v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_kernel, dim3(blocks_for(n)), dim3(kThreads), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t symmetrize_pairs(double* x, int nh, int np, hipStream_t st) {
+  const long n = (long)nh * nh * np * np;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(symmetrize_kernel, dim3(blocks_for(n)), dim3(kThreads), 0, st, x, nh, np);
+  return hipGetLastError();
+}
+
+hipError_t mask_active(double* r1, double* r2, int nc, int na, int nv, hipStream_t st) {
+  const long n = (long)na * na * na * na + (long)na * na;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(mask_kernel, dim3(blocks_for(n)), dim3(kThreads), 0, st, r1, r2, nc, na, nc + na, na + nv);
+  return hipGetLastError();
+}
+
+hipError_t dot_accumulate(const double* a, const double* b, long n, double alpha, double* out, double* partial,
+                          hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(dot_partial, dim3(kRedBlocks), dim3(kThreads), 0, st, a, b, n, partial);
+  hipLaunchKernelGGL(finish_sum, dim3(1), dim3(kThreads), 0, st, partial, kRedBlocks, alpha, out, 1);
+  return hipGetLastError();
+}
+
+hipError_t ric_update_kernel(double* t1, double* t2, const double* r1, const double* r2, const double* eps, int nc,
+                             int na, int nv, double s, double* partial, double* norm2, hipStream_t st) {
+  hipLaunchKernelGGL(update_kernel, dim3(kRedBlocks), dim3(kThreads), 0, st, t1, t2, r1, r2, eps, nc, na, nv, s,
+                     partial);
+  hipLaunchKernelGGL(finish_sum, dim3(1), dim3(kThreads), 0, st, partial, kRedBlocks, 1.0, norm2, 0);
+  return hipGetLastError();
+}
+
+hipError_t fock_diagonal(const double* f, int n, double* eps, hipStream_t st) {
+  hipLaunchKernelGGL(diag_kernel, dim3(blocks_for(n)), dim3(kThreads), 0, st, f, n, eps);
+  return hipGetLastError();
+}
+
+hipError_t check_finite(const double* x, long n, int* flag, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(nonfinite_kernel, dim3(blocks_for(n)), dim3(kThreads), 0, st, x, n, flag);
+  return hipGetLastError();
+}
+
+hipError_t prepare_cumulants(const double* g1, const double* g2, const double* g3, int na, double* ga, double* ea,
+                             double* l2, double* k2, double* l3, double* k3, hipStream_t st) {
+  if (na <= 0) return hipSuccess;
+  const long n4 = (long)na * na * na * na, n6 = n4 * na * na;
+  hipLaunchKernelGGL(onebody_kernel, dim3(blocks_for(na * na)), dim3(kThreads), 0, st, g1, na, ga, ea);
+  hipLaunchKernelGGL(lambda2_kernel, dim3(blocks_for(n4)), dim3(kThreads), 0, st, g1, g2, na, l2);
+  hipLaunchKernelGGL(k2_kernel, dim3(blocks_for(n4)), dim3(kThreads), 0, st, l2, na, k2);
+  hipLaunchKernelGGL(lambda3_kernel, dim3(blocks_for(n6)), dim3(kThreads), 0, st, g1, l2, g3, na, l3);
+  hipLaunchKernelGGL(k3_kernel, dim3(blocks_for(n6)), dim3(kThreads), 0, st, l3, na, k3);
+  return hipGetLastError();
+}
+
+hipError_t reference_energy(const double* f, int n, const double* I4, int nc, int na, const double* g1,
+                            const double* g2, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(e0_kernel, dim3(1), dim3(kThreads), 0, st, f, n, I4, nc, na, g1, g2, out);
+  return hipGetLastError();
+}
+
+hipError_t ladder_scatter_add(const double* C, int nh, int np, int c0, int c1, int ncol, double* r2, hipStream_t st) {
+  const long n = (long)nh * nh * (c1 - c0) * ncol;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(ladder_scatter, dim3(blocks_for(n)), dim3(kThreads), 0, st, C, nh, np, c0, c1, ncol, r2);
+  return hipGetLastError();
+}
+
+}  // namespace ric

@@ -1,0 +1,1006 @@
+// Host runtime of the residual engine: plan loading, tensor views, contraction
+// execution (index permutation + MFMA GEMM), DF-chunked integrals, the
+// particle-particle ladder, and the C ABI declared in include/ricmrcc.h.
+#include <hip/hip_runtime.h>
+#include <dlfcn.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <functional>
+#include <map>
+#include <memory>
+#include <sstream>
+#include <stdexcept>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/ricmrcc.h"
+#include "gemm.h"
+#include "kernels.h"
+
+namespace {
+
+using ric::GemmArgs;
+using ric::Iter;
+using ric::kMaxDims;
+
+// ---- ranges ---------------------------------------------------------------------------
+enum Rng { RC = 0, RA, RV, RH, RP, RG, RX, NRNG };
+
+Rng rng_of(char c) {
+  switch (c) {
+    case 'C': return RC;
+    case 'A': return RA;
+    case 'V': return RV;
+    case 'H': return RH;
+    case 'P': return RP;
+    case 'G': return RG;
+    case 'X': return RX;
+  }
+  throw std::runtime_error(std::string("bad range letter ") + c);
+}
+
+struct Sizes {
+  int nc = 0, na = 0, nv = 0, naux = 0;
+  long ext(Rng r) const {
+    switch (r) {
+      case RC: return nc;
+      case RA: return na;
+      case RV: return nv;
+      case RH: return nc + na;
+      case RP: return na + nv;
+      case RG: return nc + na + nv;
+      case RX: return naux;
+      default: return 0;
+    }
+  }
+  // offset of sub-range s inside declared range d
+  long off(Rng d, Rng s) const {
+    if (d == s) return 0;
+    if (d == RG) {
+      if (s == RC || s == RH) return 0;
+      if (s == RA || s == RP) return nc;
+      if (s == RV) return nc + na;
+    }
+    if (d == RH) {
+      if (s == RC) return 0;
+      if (s == RA) return nc;
+    }
+    if (d == RP) {
+      if (s == RA) return 0;
+      if (s == RV) return na;
+    }
+    throw std::runtime_error("sub-range not inside declared range");
+  }
+};
+
+struct Err : std::runtime_error {
+  int code;
+  Err(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIPCHK(x)                                                                        \
+  do {                                                                                   \
+    hipError_t e_ = (x);                                                                 \
+    if (e_ != hipSuccess)                                                                \
+      throw Err(e_ == hipErrorOutOfMemory ? RIC_E_OOM : RIC_E_HIP,                       \
+                std::string(#x) + ": " + hipGetErrorString(e_));                         \
+  } while (0)
+
+// ---- plan -------------------------------------------------------------------------------
+struct Opd {
+  int slot = -1;
+  std::vector<Rng> sub;
+  std::vector<int> lab;
+};
+
+enum Kind { K_ZERO, K_ALLOC, K_FREE, K_CONTRACT, K_CONTRACT0, K_ADD, K_DFC, K_SYMM, K_LADDER, K_MASK };
+
+struct Op {
+  Kind kind;
+  double alpha = 1.0;
+  std::vector<Opd> o;
+  int slot = -1;
+  std::vector<Rng> decl;  // for ALLOC
+};
+
+struct Slot {
+  std::string name;
+  std::vector<Rng> decl;
+  double* ptr = nullptr;
+};
+
+struct View {
+  double* p = nullptr;
+  int nd = 0;
+  long ext[kMaxDims];
+  long str[kMaxDims];
+  int lab[kMaxDims];
+  int find(int l) const {
+    for (int i = 0; i < nd; ++i)
+      if (lab[i] == l) return i;
+    return -1;
+  }
+  long size() const {
+    long s = 1;
+    for (int i = 0; i < nd; ++i) s *= ext[i];
+    return s;
+  }
+};
+
+double parse_frac(const std::string& s) {
+  auto k = s.find('/');
+  if (k == std::string::npos) return std::stod(s);
+  return std::stod(s.substr(0, k)) / std::stod(s.substr(k + 1));
+}
+
+// ---- device memory ----------------------------------------------------------------------
+struct DevBuf {
+  double* p = nullptr;
+  size_t n = 0;
+  void ensure(size_t elems) {
+    if (elems <= n) return;
+    if (p) HIPCHK(hipFree(p));
+    p = nullptr;
+    n = 0;
+    HIPCHK(hipMalloc(&p, std::max<size_t>(elems, 1) * sizeof(double)));
+    n = elems;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+};
+
+// caching allocator for plan intermediates: exact-size free lists
+struct Pool {
+  std::multimap<size_t, double*> free_;
+  std::vector<std::pair<double*, size_t>> all_;
+  double* get(size_t elems) {
+    elems = std::max<size_t>(elems, 1);
+    auto it = free_.find(elems);
+    if (it != free_.end()) {
+      double* p = it->second;
+      free_.erase(it);
+      return p;
+    }
+    double* p = nullptr;
+    HIPCHK(hipMalloc(&p, elems * sizeof(double)));
+    all_.push_back({p, elems});
+    return p;
+  }
+  void put(double* p, size_t elems) { free_.insert({std::max<size_t>(elems, 1), p}); }
+  void release() {
+    for (auto& a : all_) (void)hipFree(a.first);
+    all_.clear();
+    free_.clear();
+  }
+};
+
+}  // namespace
+
+struct ric_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  Sizes sz;
+  bool spaces = false, have_f = false, have_B = false, have_rdm = false;
+
+  // plan
+  std::vector<std::string> plan_lines;
+  std::vector<Slot> slots;
+  std::unordered_map<std::string, int> slot_of;
+  std::vector<Op> residual_ops, energy_ops;
+
+  // owned device tensors
+  DevBuf f, eps, B, BT, BT32, g1, g2, g3, ga, ea, l2, k2, l3, k3, I4, I3, IJ, IK, tau, Edev, red, e0;
+  DevBuf scrA, scrB, scrC, scrK, wbuf, lad32, dfa, dfb;
+  Pool pool;
+  int precision = RIC_FP64;
+  double ladder_ms = 0.0, total_ms = 0.0;
+  bool ladder_ran = false;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+
+  ~ric_ctx() {
+    for (DevBuf* b : {&f, &eps, &B, &BT, &BT32, &g1, &g2, &g3, &ga, &ea, &l2, &k2, &l3, &k3, &I4, &I3, &IJ, &IK,
+                      &tau, &Edev, &red, &e0, &scrA, &scrB, &scrC, &scrK, &wbuf, &lad32, &dfa, &dfb})
+      b->release();
+    pool.release();
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+
+  // -- plan parsing ---------------------------------------------------------------------
+  int slot(const std::string& name, const std::vector<Rng>* decl = nullptr) {
+    auto it = slot_of.find(name);
+    if (it != slot_of.end()) return it->second;
+    Slot s;
+    s.name = name;
+    if (decl) s.decl = *decl;
+    slots.push_back(s);
+    slot_of[name] = (int)slots.size() - 1;
+    return (int)slots.size() - 1;
+  }
+
+  Opd parse_opd(const std::string& tok, std::map<std::string, int>& labels) {
+    auto a = tok.find(':');
+    auto b = tok.find(':', a + 1);
+    if (a == std::string::npos || b == std::string::npos) throw Err(RIC_E_PLAN, "bad operand " + tok);
+    Opd o;
+    o.slot = slot(tok.substr(0, a));
+    for (char c : tok.substr(a + 1, b - a - 1)) o.sub.push_back(rng_of(c));
+    std::string ls = tok.substr(b + 1);
+    std::stringstream ss(ls);
+    std::string item;
+    while (std::getline(ss, item, ',')) {
+      if (item.empty()) continue;
+      auto it = labels.find(item);
+      int id;
+      if (it == labels.end()) {
+        id = (int)labels.size();
+        labels[item] = id;
+      } else {
+        id = it->second;
+      }
+      o.lab.push_back(id);
+    }
+    if (o.lab.size() != o.sub.size()) throw Err(RIC_E_PLAN, "label/range count mismatch in " + tok);
+    return o;
+  }
+
+  void load_plan(const std::string& path) {
+    std::ifstream in(path);
+    if (!in) throw Err(RIC_E_PLAN, "cannot open plan " + path);
+    auto decl = [](const char* s) {
+      std::vector<Rng> v;
+      for (; *s; ++s) v.push_back(rng_of(*s));
+      return v;
+    };
+    struct D { const char* n; const char* r; };
+    const D fixed[] = {{"f", "GG"},     {"B", "XGG"},    {"T1", "HP"},   {"T2", "HHPP"}, {"gA", "AA"},
+                       {"eA", "AA"},    {"K2", "AAAA"},  {"K3", "AAAAAA"}, {"I4", "HHHH"}, {"I3", "HHHP"},
+                       {"IJ", "HHPP"},  {"IK", "HPHP"},  {"R1", "HP"},   {"R2", "HHPP"}, {"TAU", "HHPP"},
+                       {"E", ""}};
+    for (auto& d : fixed) {
+      auto v = decl(d.r);
+      slot(d.n, &v);
+    }
+    std::string line;
+    std::vector<Op>* cur = nullptr;
+    while (std::getline(in, line)) {
+      if (line.empty() || line[0] == '#') continue;
+      std::stringstream ss(line);
+      std::vector<std::string> t;
+      std::string w;
+      while (ss >> w) t.push_back(w);
+      if (t.empty()) continue;
+      if (t[0] == "SECTION") {
+        cur = t.at(1) == "residual" ? &residual_ops : &energy_ops;
+        continue;
+      }
+      if (t[0] == "END") {
+        cur = nullptr;
+        continue;
+      }
+      if (!cur) throw Err(RIC_E_PLAN, "operation outside a section: " + line);
+      Op op;
+      std::map<std::string, int> labels;
+      if (t[0] == "ALLOC") {
+        op.kind = K_ALLOC;
+        auto v = decl(t.at(2).c_str());
+        op.slot = slot(t.at(1), &v);
+        slots[op.slot].decl = v;
+        op.decl = v;
+      } else if (t[0] == "FREE") {
+        op.kind = K_FREE;
+        op.slot = slot(t.at(1));
+      } else if (t[0] == "ZERO") {
+        op.kind = K_ZERO;
+        op.slot = slot(t.at(1));
+      } else if (t[0] == "CONTRACT" || t[0] == "CONTRACT0") {
+        op.kind = t[0] == "CONTRACT" ? K_CONTRACT : K_CONTRACT0;
+        op.alpha = parse_frac(t.at(1));
+        for (int i = 2; i < 5; ++i) op.o.push_back(parse_opd(t.at(i), labels));
+      } else if (t[0] == "ADD") {
+        op.kind = K_ADD;
+        op.alpha = parse_frac(t.at(1));
+        for (int i = 2; i < 4; ++i) op.o.push_back(parse_opd(t.at(i), labels));
+      } else if (t[0] == "DFC") {
+        op.kind = K_DFC;
+        op.alpha = parse_frac(t.at(1));
+        for (int i = 2; i < 6; ++i) op.o.push_back(parse_opd(t.at(i), labels));
+      } else if (t[0] == "SYMMETRIZE") {
+        op.kind = K_SYMM;
+        op.slot = slot(t.at(1));
+      } else if (t[0] == "LADDER") {
+        op.kind = K_LADDER;
+      } else if (t[0] == "MASK") {
+        op.kind = K_MASK;
+      } else {
+        throw Err(RIC_E_PLAN, "unknown plan operation " + t[0]);
+      }
+      cur->push_back(op);
+    }
+    if (residual_ops.empty()) throw Err(RIC_E_PLAN, "plan has no residual section");
+  }
+
+  // -- views ------------------------------------------------------------------------------
+  View view(const Opd& o) {
+    const Slot& s = slots.at(o.slot);
+    bool empty = false;
+    for (Rng r : o.sub) empty = empty || sz.ext(r) == 0;
+    if (!s.ptr && s.decl.size() > 0 && !empty) throw Err(RIC_E_STATE, "tensor " + s.name + " is not available");
+    View v;
+    v.nd = (int)o.sub.size();
+    if (v.nd != (int)s.decl.size()) throw Err(RIC_E_PLAN, "rank mismatch for " + s.name);
+    long stride = 1;
+    long full[kMaxDims];
+    for (int i = v.nd - 1; i >= 0; --i) {
+      full[i] = stride;
+      stride *= sz.ext(s.decl[i]);
+    }
+    long off = 0;
+    for (int i = 0; i < v.nd; ++i) {
+      v.ext[i] = sz.ext(o.sub[i]);
+      v.str[i] = full[i];
+      v.lab[i] = o.lab[i];
+      off += sz.off(s.decl[i], o.sub[i]) * full[i];
+    }
+    v.p = empty ? nullptr : s.ptr + off;
+    return v;
+  }
+
+  long slot_elems(int id) {
+    long n = 1;
+    for (Rng r : slots[id].decl) n *= sz.ext(r);
+    return n;
+  }
+
+  // -- primitive: out[lab order] (beta) += alpha * in[perm] ------------------------------------
+  void axpby(const View& out, double alpha, const View& in, double beta) {
+    Iter it;
+    it.nd = out.nd;
+    it.total = 1;
+    for (int i = 0; i < out.nd; ++i) {
+      it.ext[i] = out.ext[i];
+      it.so[i] = out.str[i];
+      int j = in.find(out.lab[i]);
+      if (j < 0) throw Err(RIC_E_PLAN, "ADD: label missing in input");
+      it.si[i] = in.str[j];
+      it.total *= out.ext[i];
+    }
+    if (in.nd != out.nd) throw Err(RIC_E_PLAN, "ADD: rank mismatch");
+    if (it.nd == 0) it.total = 1;
+    HIPCHK(ric::strided_copy(it, alpha, in.p, beta, out.p, stream));
+  }
+
+  // gather view dims in the given order into a contiguous buffer
+  void gather(const View& v, const std::vector<int>& order, double* dst, float* dst32) {
+    Iter it;
+    it.nd = (int)order.size();
+    it.total = 1;
+    long st = 1;
+    for (int i = it.nd - 1; i >= 0; --i) {
+      it.ext[i] = v.ext[order[i]];
+      it.si[i] = v.str[order[i]];
+      it.so[i] = st;
+      st *= it.ext[i];
+    }
+    it.total = st;
+    if (dst32) HIPCHK(ric::strided_copy_f32(it, 1.0, v.p, dst32, stream));
+    else HIPCHK(ric::strided_copy(it, 1.0, v.p, 0.0, dst, stream));
+  }
+
+  // dims (in order) mergeable into one index of stride `s` (product extent)?
+  static bool mergeable(const View& v, const std::vector<int>& dims, long& s) {
+    s = 1;
+    if (dims.empty()) return true;
+    long expect = -1;
+    for (int i = (int)dims.size() - 1; i >= 0; --i) {
+      const int d = dims[i];
+      if (v.ext[d] == 1) continue;
+      if (expect < 0) {
+        s = v.str[d];
+        expect = v.str[d] * v.ext[d];
+      } else {
+        if (v.str[d] != expect) return false;
+        expect = v.str[d] * v.ext[d];
+      }
+    }
+    return true;
+  }
+
+  // -- contraction out (+)= alpha * sum a * b -------------------------------------------------
+  void contract(const View& out, double alpha, const View& a, const View& b, bool fresh, bool allow32) {
+    std::vector<int> aM, aK, bN, bK, oM, oN;
+    for (int i = 0; i < out.nd; ++i) {
+      const int l = out.lab[i];
+      const int ia = a.find(l), ib = b.find(l);
+      if (ia >= 0 && ib >= 0) throw Err(RIC_E_PLAN, "batch labels are not supported");
+      if (ia >= 0) {
+        aM.push_back(ia);
+        oM.push_back(i);
+      } else if (ib >= 0) {
+        bN.push_back(ib);
+        oN.push_back(i);
+      } else {
+        throw Err(RIC_E_PLAN, "output label not in operands");
+      }
+    }
+    for (int i = 0; i < a.nd; ++i) {
+      const int l = a.lab[i];
+      if (out.find(l) >= 0) continue;
+      const int ib = b.find(l);
+      if (ib < 0) throw Err(RIC_E_PLAN, "label summed in one operand only");
+      aK.push_back(i);
+      bK.push_back(ib);
+    }
+    for (int i = 0; i < b.nd; ++i)
+      if (out.find(b.lab[i]) < 0 && a.find(b.lab[i]) < 0) throw Err(RIC_E_PLAN, "label summed in one operand only");
+    long M = 1, N = 1, K = 1;
+    for (int d : aM) M *= a.ext[d];
+    for (int d : bN) N *= b.ext[d];
+    for (int d : aK) K *= a.ext[d];
+    if (M == 0 || N == 0) return;
+    if (K == 0) {
+      if (fresh) HIPCHK(ric::fill(out.p, out.size(), 0.0, stream));  // fresh outputs are contiguous
+      return;
+    }
+    const double flops = 2.0 * (double)M * N * K;
+    const bool use32 = allow32 && precision == RIC_FP32MIX && flops > 1e10;
+
+    // energy-type full contraction: dot product
+    if (M == 1 && N == 1 && !use32) {
+      std::vector<int> ka = aK, kb = bK;
+      const double* pa;
+      const double* pb;
+      long sa, sb;
+      bool ca = mergeable(a, ka, sa) && sa == 1;
+      bool cb = mergeable(b, kb, sb) && sb == 1;
+      scrA.ensure(ca ? 0 : K);
+      scrB.ensure(cb ? 0 : K);
+      if (ca) pa = a.p; else { gather(a, ka, scrA.p, nullptr); pa = scrA.p; }
+      if (cb) pb = b.p; else { gather(b, kb, scrB.p, nullptr); pb = scrB.p; }
+      red.ensure(1024);
+      if (fresh) HIPCHK(ric::fill(out.p, 1, 0.0, stream));
+      HIPCHK(ric::dot_accumulate(pa, pb, K, alpha, out.p, red.p, stream));
+      return;
+    }
+
+    // operand A as [M][K], B as [N][K]
+    std::vector<int> ordA = aM, ordB = bN;
+    ordA.insert(ordA.end(), aK.begin(), aK.end());
+    ordB.insert(ordB.end(), bK.begin(), bK.end());
+    long sAm, sAk, sBn, sBk;
+    bool directA = !use32 && mergeable(a, aM, sAm) && mergeable(a, aK, sAk) && sAk == 1;
+    bool directB = !use32 && mergeable(b, bN, sBn) && mergeable(b, bK, sBk) && sBk == 1;
+    if (directA && M > 1 && sAm < K) directA = false;
+    if (directB && N > 1 && sBn < K) directB = false;
+    if (M == 1) sAm = K;
+    if (N == 1) sBn = K;
+    // output as [M][N]
+    long sOm, sOn;
+    bool directC = mergeable(out, oM, sOm) && mergeable(out, oN, sOn) && (sOn == 1 || N == 1);
+    if (directC && M > 1 && N > 1 && sOm < N) directC = false;
+    if (M == 1) sOm = N;
+
+    if (!directA) scrA.ensure(use32 ? ((size_t)M * K + 1) / 2 : (size_t)M * K);
+    if (!directB) scrB.ensure(use32 ? ((size_t)N * K + 1) / 2 : (size_t)N * K);
+    const double* pA = a.p;
+    const double* pB = b.p;
+    if (!directA) {
+      gather(a, ordA, use32 ? nullptr : scrA.p, use32 ? reinterpret_cast<float*>(scrA.p) : nullptr);
+      pA = scrA.p;
+      sAm = K;
+    }
+    if (!directB) {
+      gather(b, ordB, use32 ? nullptr : scrB.p, use32 ? reinterpret_cast<float*>(scrB.p) : nullptr);
+      pB = scrB.p;
+      sBn = K;
+    }
+    GemmArgs g;
+    g.M = (int)M;
+    g.N = (int)N;
+    g.K = (int)K;
+    if (M > 2147483647L || N > 2147483647L || K > 2147483647L) throw Err(RIC_E_ARG, "contraction too large");
+    g.lda = sAm;
+    g.ldb = sBn;
+    scrK.ensure(64L * 1024 * 1024);
+    if (directC) {
+      g.alpha = alpha;
+      g.beta = fresh ? 0.0 : 1.0;
+      g.C = out.p;
+      g.ldc = sOm;
+    } else {
+      scrC.ensure((size_t)M * N);
+      g.alpha = 1.0;
+      g.beta = 0.0;
+      g.C = scrC.p;
+      g.ldc = N;
+    }
+    if (use32)
+      HIPCHK(ric::gemm_nt_f32(g, reinterpret_cast<const float*>(pA), reinterpret_cast<const float*>(pB), stream,
+                              scrK.p, scrK.n));
+    else
+      HIPCHK(ric::gemm_nt_f64(g, pA, pB, stream, scrK.p, scrK.n));
+    if (!directC) {
+      // out[dims] (+)= alpha * Ctmp[M][N]
+      Iter it;
+      it.nd = out.nd;
+      it.total = 1;
+      long stM[kMaxDims], stN[kMaxDims];
+      {
+        long s = N;
+        for (int i = (int)oM.size() - 1; i >= 0; --i) { stM[i] = s; s *= out.ext[oM[i]]; }
+        s = 1;
+        for (int i = (int)oN.size() - 1; i >= 0; --i) { stN[i] = s; s *= out.ext[oN[i]]; }
+      }
+      for (int i = 0; i < out.nd; ++i) {
+        it.ext[i] = out.ext[i];
+        it.so[i] = out.str[i];
+        it.total *= out.ext[i];
+        auto pm = std::find(oM.begin(), oM.end(), i);
+        if (pm != oM.end()) it.si[i] = stM[pm - oM.begin()];
+        else it.si[i] = stN[std::find(oN.begin(), oN.end(), i) - oN.begin()];
+      }
+      HIPCHK(ric::strided_copy(it, alpha, scrC.p, fresh ? 0.0 : 1.0, out.p, stream));
+    }
+  }
+
+  // -- (pr|qs) = sum_X L1[X,p,r] L2[X,q,s] built block by block and contracted with y ---------
+  void dfc(const View& out, double alpha, const View& L1, const View& L2, const View& y) {
+    const long np_ = L1.ext[1], nr = L1.ext[2], nq = L2.ext[1], ns = L2.ext[2], nx = L1.ext[0];
+    if (np_ == 0 || nr == 0 || nq == 0 || ns == 0) return;
+    // L2 as [(q,s)][X]
+    DevBuf& l2buf = dfb;
+    l2buf.ensure((size_t)nq * ns * nx);
+    gather(L2, {1, 2, 0}, l2buf.p, nullptr);
+    const long per = std::max<long>(1, (long)(1.2e9 / std::max<long>(1, nr * nq * ns)));
+    const long chunk = std::min(np_, per);
+    const int lp = L1.lab[1];
+    for (long p0 = 0; p0 < np_; p0 += chunk) {
+      const long pc = std::min(chunk, np_ - p0);
+      View l1c = L1;
+      l1c.p += p0 * L1.str[1];
+      l1c.ext[1] = pc;
+      dfa.ensure((size_t)pc * nr * nx);
+      gather(l1c, {1, 2, 0}, dfa.p, nullptr);
+      wbuf.ensure((size_t)pc * nr * nq * ns);
+      GemmArgs g;
+      g.M = (int)(pc * nr);
+      g.N = (int)(nq * ns);
+      g.K = (int)nx;
+      g.lda = nx;
+      g.ldb = nx;
+      g.C = wbuf.p;
+      g.ldc = nq * ns;
+      scrK.ensure(64L * 1024 * 1024);
+      HIPCHK(ric::gemm_nt_f64(g, dfa.p, l2buf.p, stream, scrK.p, scrK.n));
+      View e;
+      e.p = wbuf.p;
+      e.nd = 4;
+      const long ex[4] = {pc, nr, nq, ns};
+      const int lb[4] = {lp, L1.lab[2], L2.lab[1], L2.lab[2]};
+      long st = 1;
+      for (int i = 3; i >= 0; --i) {
+        e.ext[i] = ex[i];
+        e.str[i] = st;
+        e.lab[i] = lb[i];
+        st *= ex[i];
+      }
+      View oc = out, yc = y;
+      for (View* v : {&oc, &yc}) {
+        int d = v->find(lp);
+        if (d >= 0) {
+          v->p += p0 * v->str[d];
+          v->ext[d] = pc;
+        }
+      }
+      contract_keep_scratch(oc, alpha, e, yc);
+    }
+  }
+
+  // contraction whose operand `e` lives in wbuf and must not be overwritten by gathers
+  void contract_keep_scratch(const View& out, double alpha, const View& e, const View& y) {
+    // e is contiguous; the contraction only gathers into scrA/scrB/scrC, never wbuf
+    contract(out, alpha, e, y, false, true);
+  }
+
+  // -- ladder: R2[k,l,c,d] += sum_{e,f} (ce|df) tau[k,l,e,f] ------------------------------------
+  void ladder(const double* taup, double* r2) {
+    const int nc = sz.nc, np_ = sz.na + sz.nv, nh = sz.nc + sz.na, nx = sz.naux;
+    if (np_ == 0 || nh == 0) return;
+    const long pp = (long)np_ * np_;
+    const bool mixed = precision == RIC_FP32MIX;
+    if (BT.n < (size_t)pp * nx) throw Err(RIC_E_STATE, "DF factors not loaded");
+    // tau in fp32 for the mixed path
+    const float* tau32 = nullptr;
+    if (mixed) {
+      lad32.ensure(((size_t)nh * nh * pp + 1) / 2);
+      Iter it;
+      it.nd = 1;
+      it.total = (long)nh * nh * pp;
+      it.ext[0] = it.total;
+      it.so[0] = 1;
+      it.si[0] = 1;
+      HIPCHK(ric::strided_copy_f32(it, 1.0, taup, reinterpret_cast<float*>(lad32.p), stream));
+      tau32 = reinterpret_cast<const float*>(lad32.p);
+    }
+    // chunk of c rows: W[(c - c0), d, e, f] for d < c1
+    const double budget = 1.6e9;  // elements of W per chunk
+    long chunk = std::max<long>(1, (long)(budget / ((double)np_ * pp)));
+    chunk = std::min<long>(chunk, np_);
+    const size_t welems = (size_t)chunk * np_ * pp;
+    wbuf.ensure(mixed ? (welems + 1) / 2 : welems);
+    scrC.ensure((size_t)nh * nh * chunk * np_);
+    scrK.ensure(64L * 1024 * 1024);
+    for (int c0 = 0; c0 < np_; c0 += (int)chunk) {
+      const int c1 = std::min<int>(np_, c0 + (int)chunk);
+      const int rows = c1 - c0;
+      // W build: batch z = (c - c0) * c1 + d
+      GemmArgs g;
+      g.M = np_;
+      g.N = np_;
+      g.K = nx;
+      g.lda = nx;
+      g.ldb = nx;
+      g.ldc = np_;
+      g.batch = rows * c1;
+      g.zdiv = c1;
+      g.strideA = (long)np_ * nx;
+      g.strideB = (long)np_ * nx;
+      g.strideC = pp;
+      if (!mixed) {
+        g.C = wbuf.p;
+        HIPCHK(ric::gemm_nt_f64(g, BT.p + (long)c0 * np_ * nx, BT.p, stream, scrK.p, scrK.n));
+      } else {
+        HIPCHK(ric::gemm_nt_f32_out32(g, reinterpret_cast<const float*>(BT32.p) + (long)c0 * np_ * nx,
+                                      reinterpret_cast<const float*>(BT32.p), reinterpret_cast<float*>(wbuf.p),
+                                      stream));
+      }
+      // contraction: C[kl][(c - c0) * c1 + d] = sum_ef tau[kl][ef] W[(c,d)][ef]
+      GemmArgs h;
+      h.M = nh * nh;
+      h.N = rows * c1;
+      h.K = (int)pp;
+      h.lda = pp;
+      h.ldb = pp;
+      h.C = scrC.p;
+      h.ldc = h.N;
+      if (!mixed)
+        HIPCHK(ric::gemm_nt_f64(h, taup, wbuf.p, stream, scrK.p, scrK.n));
+      else
+        HIPCHK(ric::gemm_nt_f32(h, tau32, reinterpret_cast<const float*>(wbuf.p), stream, scrK.p, scrK.n));
+      HIPCHK(ric::ladder_scatter_add(scrC.p, nh, np_, c0, c1, c1, r2, stream));
+    }
+    (void)nc;
+  }
+
+  // -- plan execution -----------------------------------------------------------------------
+  void run(std::vector<Op>& ops) {
+    for (Op& op : ops) {
+      switch (op.kind) {
+        case K_ALLOC: {
+          Slot& s = slots[op.slot];
+          s.decl = op.decl;
+          s.ptr = pool.get((size_t)slot_elems(op.slot));
+          break;
+        }
+        case K_FREE: {
+          Slot& s = slots[op.slot];
+          pool.put(s.ptr, (size_t)slot_elems(op.slot));
+          s.ptr = nullptr;
+          break;
+        }
+        case K_ZERO: {
+          Slot& s = slots[op.slot];
+          HIPCHK(ric::fill(s.ptr, slot_elems(op.slot), 0.0, stream));
+          break;
+        }
+        case K_CONTRACT:
+        case K_CONTRACT0:
+          contract(view(op.o[0]), op.alpha, view(op.o[1]), view(op.o[2]), op.kind == K_CONTRACT0, true);
+          break;
+        case K_ADD:
+          axpby(view(op.o[0]), op.alpha, view(op.o[1]), 1.0);
+          break;
+        case K_DFC:
+          dfc(view(op.o[0]), op.alpha, view(op.o[1]), view(op.o[2]), view(op.o[3]));
+          break;
+        case K_SYMM:
+          HIPCHK(ric::symmetrize_pairs(slots[op.slot].ptr, sz.nc + sz.na, sz.na + sz.nv, stream));
+          break;
+        case K_LADDER: {
+          HIPCHK(hipEventRecord(ev[0], stream));
+          ladder(slots[slot_of["TAU"]].ptr, slots[slot_of["R2"]].ptr);
+          HIPCHK(hipEventRecord(ev[1], stream));
+          ladder_ran = true;
+          break;
+        }
+        case K_MASK:
+          HIPCHK(ric::mask_active(slots[slot_of["R1"]].ptr, slots[slot_of["R2"]].ptr, sz.nc, sz.na, sz.nv, stream));
+          break;
+      }
+    }
+  }
+
+  void bind(const char* name, const double* p) { slots[slot_of.at(name)].ptr = const_cast<double*>(p); }
+
+  void require_loaded() {
+    if (!spaces) throw Err(RIC_E_STATE, "ric_set_spaces has not been called");
+    if (!have_f || !have_B) throw Err(RIC_E_STATE, "Fock matrix and DF factors must be loaded");
+    if (sz.na > 0 && !have_rdm) throw Err(RIC_E_STATE, "RDMs must be loaded when na > 0");
+  }
+};
+
+namespace {
+
+std::string default_plan_path() {
+  Dl_info info;
+  if (dladdr(reinterpret_cast<void*>(&default_plan_path), &info) && info.dli_fname) {
+    std::string p(info.dli_fname);
+    auto k = p.rfind('/');
+    std::string dir = k == std::string::npos ? "." : p.substr(0, k);
+    return dir + "/plan.txt";
+  }
+  return "plan.txt";
+}
+
+}  // namespace
+
+namespace {
+int guard(ric_ctx* ctx, const std::function<void()>& fn) {
+  if (!ctx) return RIC_E_ARG;
+  try {
+    HIPCHK(hipSetDevice(ctx->device));
+    (void)hipGetLastError();  // clear a stale error left by an earlier failed call
+    fn();
+    ctx->err.clear();
+    return RIC_OK;
+  } catch (const Err& e) {
+    ctx->err = e.what();
+    return e.code;
+  } catch (const std::exception& e) {
+    ctx->err = e.what();
+    return RIC_E_ARG;
+  }
+}
+}  // namespace
+
+extern "C" {
+
+int ric_create(ric_ctx** out, int device, void* hip_stream, const char* plan_path) {
+  if (!out) return RIC_E_ARG;
+  *out = nullptr;
+  auto* ctx = new (std::nothrow) ric_ctx();
+  if (!ctx) return RIC_E_OOM;
+  ctx->device = device;
+  ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  int rc = guard(ctx, [&] {
+    for (auto& e : ctx->ev) HIPCHK(hipEventCreate(&e));
+    ctx->load_plan(plan_path ? std::string(plan_path) : default_plan_path());
+  });
+  if (rc != RIC_OK) {
+    fprintf(stderr, "ric_create: %s\n", ctx->err.c_str());
+    delete ctx;
+    return rc;
+  }
+  *out = ctx;
+  return RIC_OK;
+}
+
+void ric_destroy(ric_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  delete ctx;
+}
+
+int ric_set_spaces(ric_ctx* ctx, int nc, int na, int nv, int naux) {
+  return guard(ctx, [&] {
+    if (nc < 0 || na < 0 || nv < 0 || naux < 1 || na > 16 || nc + na < 1 || na + nv < 1)
+      throw Err(RIC_E_ARG, "invalid orbital space sizes");
+    ctx->sz = Sizes{nc, na, nv, naux};
+    ctx->spaces = true;
+    ctx->have_f = ctx->have_B = ctx->have_rdm = false;
+  });
+}
+
+int ric_load_fock(ric_ctx* ctx, const double* f) {
+  return guard(ctx, [&] {
+    if (!ctx->spaces) throw Err(RIC_E_STATE, "ric_set_spaces has not been called");
+    if (!f) throw Err(RIC_E_ARG, "null Fock matrix");
+    const long n = ctx->sz.ext(RG);
+    ctx->f.ensure(n * n);
+    HIPCHK(hipMemcpyAsync(ctx->f.p, f, n * n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    ctx->eps.ensure(n);
+    HIPCHK(ric::fock_diagonal(ctx->f.p, (int)n, ctx->eps.p, ctx->stream));
+    ctx->bind("f", ctx->f.p);
+    ctx->have_f = true;
+  });
+}
+
+int ric_load_df(ric_ctx* ctx, const double* B) {
+  return guard(ctx, [&] {
+    if (!ctx->spaces) throw Err(RIC_E_STATE, "ric_set_spaces has not been called");
+    if (!B) throw Err(RIC_E_ARG, "null DF factors");
+    const Sizes& s = ctx->sz;
+    const long n = s.ext(RG), nx = s.naux, nc = s.nc, np_ = s.ext(RP);
+    ctx->B.ensure((size_t)nx * n * n);
+    HIPCHK(hipMemcpyAsync(ctx->B.p, B, (size_t)nx * n * n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    ctx->bind("B", ctx->B.p);
+    // ladder operand BT[c][e][X] = B[X][nc + c][nc + e]
+    ctx->BT.ensure((size_t)np_ * np_ * nx);
+    {
+      View v;
+      v.p = ctx->B.p + nc * n + nc;
+      v.nd = 3;
+      v.ext[0] = nx; v.str[0] = n * n; v.lab[0] = 0;
+      v.ext[1] = np_; v.str[1] = n; v.lab[1] = 1;
+      v.ext[2] = np_; v.str[2] = 1; v.lab[2] = 2;
+      ctx->gather(v, {1, 2, 0}, ctx->BT.p, nullptr);
+      ctx->BT32.ensure(((size_t)np_ * np_ * nx + 1) / 2);
+      ctx->gather(v, {1, 2, 0}, nullptr, reinterpret_cast<float*>(ctx->BT32.p));
+    }
+    // stored integral blocks (pr|qs) with at most two particle indices
+    std::map<std::string, int> lab;
+    auto mk = [&](const char* nm, const char* decl, DevBuf& buf) {
+      std::vector<Rng> d;
+      for (const char* c = decl; *c; ++c) d.push_back(rng_of(*c));
+      long e = 1;
+      for (Rng r : d) e *= s.ext(r);
+      buf.ensure((size_t)e);
+      ctx->bind(nm, buf.p);
+      // (pr|qs) = sum_X B[X,p,r] B[X,q,s]
+      Opd o, b1, b2;
+      o.slot = ctx->slot_of.at(nm);
+      o.sub = d;
+      o.lab = {1, 2, 3, 4};
+      b1.slot = ctx->slot_of.at("B");
+      b1.sub = {RX, d[0], d[1]};
+      b1.lab = {0, 1, 2};
+      b2.slot = ctx->slot_of.at("B");
+      b2.sub = {RX, d[2], d[3]};
+      b2.lab = {0, 3, 4};
+      ctx->contract(ctx->view(o), 1.0, ctx->view(b1), ctx->view(b2), true, false);
+    };
+    mk("I4", "HHHH", ctx->I4);
+    mk("I3", "HHHP", ctx->I3);
+    mk("IJ", "HHPP", ctx->IJ);
+    mk("IK", "HPHP", ctx->IK);
+    ctx->have_B = true;
+  });
+}
+
+int ric_load_rdms(ric_ctx* ctx, const double* G1, const double* G2, const double* G3) {
+  return guard(ctx, [&] {
+    if (!ctx->spaces) throw Err(RIC_E_STATE, "ric_set_spaces has not been called");
+    const long na = ctx->sz.na;
+    if (na == 0) {
+      ctx->have_rdm = true;
+      return;
+    }
+    if (!G1 || !G2 || !G3) throw Err(RIC_E_ARG, "null RDM");
+    const long n2 = na * na, n4 = n2 * n2, n6 = n4 * n2;
+    ctx->g1.ensure(n2);
+    ctx->g2.ensure(n4);
+    ctx->g3.ensure(n6);
+    HIPCHK(hipMemcpyAsync(ctx->g1.p, G1, n2 * 8, hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->g2.p, G2, n4 * 8, hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->g3.p, G3, n6 * 8, hipMemcpyDeviceToDevice, ctx->stream));
+    ctx->ga.ensure(n2);
+    ctx->ea.ensure(n2);
+    ctx->l2.ensure(n4);
+    ctx->k2.ensure(n4);
+    ctx->l3.ensure(n6);
+    ctx->k3.ensure(n6);
+    HIPCHK(ric::prepare_cumulants(ctx->g1.p, ctx->g2.p, ctx->g3.p, (int)na, ctx->ga.p, ctx->ea.p, ctx->l2.p,
+                                  ctx->k2.p, ctx->l3.p, ctx->k3.p, ctx->stream));
+    ctx->bind("gA", ctx->ga.p);
+    ctx->bind("eA", ctx->ea.p);
+    ctx->bind("K2", ctx->k2.p);
+    ctx->bind("K3", ctx->k3.p);
+    ctx->have_rdm = true;
+  });
+}
+
+int ric_residual(ric_ctx* ctx, const double* T1, const double* T2, double* R1, double* R2, int precision) {
+  return guard(ctx, [&] {
+    ctx->require_loaded();
+    if (!T1 || !T2 || !R1 || !R2) throw Err(RIC_E_ARG, "null amplitude/residual pointer");
+    if (precision != RIC_FP64 && precision != RIC_FP32MIX) throw Err(RIC_E_ARG, "bad precision");
+    ctx->precision = precision;
+    ctx->bind("T1", T1);
+    ctx->bind("T2", T2);
+    ctx->bind("R1", R1);
+    ctx->bind("R2", R2);
+    ctx->ladder_ran = false;
+    HIPCHK(hipEventRecord(ctx->ev[2], ctx->stream));
+    ctx->run(ctx->residual_ops);
+    HIPCHK(hipEventRecord(ctx->ev[3], ctx->stream));
+    HIPCHK(hipEventSynchronize(ctx->ev[3]));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, ctx->ev[2], ctx->ev[3]));
+    ctx->total_ms = ms;
+    ms = 0.f;
+    if (ctx->ladder_ran) HIPCHK(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
+    ctx->ladder_ms = ms;
+  });
+}
+
+int ric_update(ric_ctx* ctx, double* T1, double* T2, const double* R1, const double* R2, double s,
+               double* step_norm2) {
+  return guard(ctx, [&] {
+    ctx->require_loaded();
+    if (!T1 || !T2 || !R1 || !R2) throw Err(RIC_E_ARG, "null amplitude/residual pointer");
+    if (!(s >= 0.0)) throw Err(RIC_E_ARG, "flow parameter must be >= 0");
+    ctx->red.ensure(1024);
+    ctx->Edev.ensure(4);
+    HIPCHK(ric::ric_update_kernel(T1, T2, R1, R2, ctx->eps.p, ctx->sz.nc, ctx->sz.na, ctx->sz.nv, s, ctx->red.p,
+                                  ctx->Edev.p + 1, ctx->stream));
+    double v = 0.0;
+    HIPCHK(hipMemcpyAsync(&v, ctx->Edev.p + 1, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (!std::isfinite(v)) throw Err(RIC_E_NONFINITE, "non-finite amplitude step");
+    if (step_norm2) *step_norm2 = v;
+  });
+}
+
+int ric_energy(ric_ctx* ctx, const double* T1, const double* T2, double* e_corr, double* e0) {
+  return guard(ctx, [&] {
+    ctx->require_loaded();
+    if (!T1 || !T2 || !e_corr) throw Err(RIC_E_ARG, "null pointer");
+    ctx->bind("T1", T1);
+    ctx->bind("T2", T2);
+    ctx->Edev.ensure(4);
+    ctx->bind("E", ctx->Edev.p);
+    ctx->precision = RIC_FP64;
+    HIPCHK(ric::fill(ctx->Edev.p, 1, 0.0, ctx->stream));
+    ctx->run(ctx->energy_ops);
+    if (e0) {
+      const double* g1 = ctx->sz.na ? ctx->g1.p : nullptr;
+      const double* g2 = ctx->sz.na ? ctx->g2.p : nullptr;
+      HIPCHK(ric::reference_energy(ctx->f.p, (int)ctx->sz.ext(RG), ctx->I4.p, ctx->sz.nc, ctx->sz.na, g1, g2,
+                                   ctx->Edev.p + 2, ctx->stream));
+    }
+    double h[4] = {0, 0, 0, 0};
+    HIPCHK(hipMemcpyAsync(h, ctx->Edev.p, 4 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (!std::isfinite(h[0])) throw Err(RIC_E_NONFINITE, "non-finite energy");
+    *e_corr = h[0];
+    if (e0) *e0 = h[2];
+  });
+}
+
+int ric_ladder(ric_ctx* ctx, const double* tau, double* R2, int precision) {
+  return guard(ctx, [&] {
+    if (!ctx->spaces || !ctx->have_B) throw Err(RIC_E_STATE, "DF factors must be loaded");
+    if (!tau || !R2) throw Err(RIC_E_ARG, "null pointer");
+    if (precision != RIC_FP64 && precision != RIC_FP32MIX) throw Err(RIC_E_ARG, "bad precision");
+    ctx->precision = precision;
+    HIPCHK(hipEventRecord(ctx->ev[0], ctx->stream));
+    ctx->ladder(tau, R2);
+    HIPCHK(hipEventRecord(ctx->ev[1], ctx->stream));
+    HIPCHK(hipEventSynchronize(ctx->ev[1]));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
+    ctx->ladder_ms = ms;
+    ctx->total_ms = ms;
+  });
+}
+
+int ric_last_timings(const ric_ctx* ctx, double* ladder_ms, double* total_ms) {
+  if (!ctx) return RIC_E_ARG;
+  if (ladder_ms) *ladder_ms = ctx->ladder_ms;
+  if (total_ms) *total_ms = ctx->total_ms;
+  return RIC_OK;
+}
+
+const char* ric_last_error(const ric_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+}  // extern "C"

@@ -1,0 +1,204 @@
+"""Python binding of the C ABI in include/ricmrcc.h (argument marshalling only).
+
+Every computation runs in the HIP library libricmrcc.so next to this file;
+there is no CPU fallback.  Device memory and streams come from PyTorch.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libricmrcc.so")
+PLAN_PATH = os.path.join(_HERE, "plan.txt")
+
+RIC_FP64 = 0
+RIC_FP32MIX = 1
+
+_ERRORS = {-1: "RIC_E_ARG", -2: "RIC_E_STATE", -3: "RIC_E_OOM", -4: "RIC_E_HIP",
+           -5: "RIC_E_NONFINITE", -6: "RIC_E_PLAN"}
+
+_lib = None
+
+
+class RicError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def library():
+    """Load libricmrcc.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library {LIB_PATH} is missing: run __graft_entry__.build() first")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    D = ctypes.c_double
+    I = ctypes.c_int
+    lib.ric_create.argtypes = [ctypes.POINTER(P), I, P, ctypes.c_char_p]
+    lib.ric_destroy.argtypes = [P]
+    lib.ric_destroy.restype = None
+    lib.ric_set_spaces.argtypes = [P, I, I, I, I]
+    lib.ric_load_fock.argtypes = [P, P]
+    lib.ric_load_df.argtypes = [P, P]
+    lib.ric_load_rdms.argtypes = [P, P, P, P]
+    lib.ric_residual.argtypes = [P, P, P, P, P, I]
+    lib.ric_update.argtypes = [P, P, P, P, P, D, ctypes.POINTER(D)]
+    lib.ric_energy.argtypes = [P, P, P, ctypes.POINTER(D), ctypes.POINTER(D)]
+    lib.ric_ladder.argtypes = [P, P, P, I]
+    lib.ric_last_timings.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(D)]
+    lib.ric_last_error.argtypes = [P]
+    lib.ric_last_error.restype = ctypes.c_char_p
+    for fn in ("ric_create", "ric_set_spaces", "ric_load_fock", "ric_load_df", "ric_load_rdms",
+               "ric_residual", "ric_update", "ric_energy", "ric_ladder", "ric_last_timings"):
+        getattr(lib, fn).restype = I
+    _lib = lib
+    return lib
+
+
+def _ptr(t, shape, name):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a GPU torch tensor")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """One residual engine on one device and stream (torch.cuda.current_stream() by default)."""
+
+    def __init__(self, device=0, stream=None, plan_path=None):
+        self.lib = library()
+        self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        path = (plan_path or PLAN_PATH).encode()
+        rc = self.lib.ric_create(ctypes.byref(h), self.device.index or 0,
+                                 ctypes.c_void_p(stream.cuda_stream), path)
+        if rc != 0:
+            raise RicError(rc, "ric_create failed")
+        self.h = h
+        self.sizes = None
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.ric_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != 0:
+            raise RicError(rc, self.lib.ric_last_error(self.h).decode())
+
+    # --- set-up -----------------------------------------------------------------------
+    def set_spaces(self, nc, na, nv, naux):
+        self._check(self.lib.ric_set_spaces(self.h, nc, na, nv, naux))
+        self.sizes = (nc, na, nv, naux)
+        self.n = nc + na + nv
+        self.nH = nc + na
+        self.nP = na + nv
+
+    def load_fock(self, f):
+        self._check(self.lib.ric_load_fock(self.h, _ptr(f, (self.n, self.n), "f")))
+
+    def load_df(self, B):
+        self._check(self.lib.ric_load_df(self.h, _ptr(B, (self.sizes[3], self.n, self.n), "B")))
+
+    def load_rdms(self, G1, G2, G3):
+        na = self.sizes[1]
+        self._check(self.lib.ric_load_rdms(
+            self.h, _ptr(G1, (na,) * 2, "G1"), _ptr(G2, (na,) * 4, "G2"), _ptr(G3, (na,) * 6, "G3")))
+
+    # --- hot path ---------------------------------------------------------------------
+    def amplitude_shapes(self):
+        return (self.nH, self.nP), (self.nH, self.nH, self.nP, self.nP)
+
+    def residual(self, T1, T2, R1, R2, precision=RIC_FP64):
+        s1, s2 = self.amplitude_shapes()
+        self._check(self.lib.ric_residual(self.h, _ptr(T1, s1, "T1"), _ptr(T2, s2, "T2"),
+                                          _ptr(R1, s1, "R1"), _ptr(R2, s2, "R2"), int(precision)))
+
+    def update(self, T1, T2, R1, R2, s):
+        s1, s2 = self.amplitude_shapes()
+        out = ctypes.c_double()
+        self._check(self.lib.ric_update(self.h, _ptr(T1, s1, "T1"), _ptr(T2, s2, "T2"), _ptr(R1, s1, "R1"),
+                                        _ptr(R2, s2, "R2"), float(s), ctypes.byref(out)))
+        return out.value
+
+    def energy(self, T1, T2):
+        s1, s2 = self.amplitude_shapes()
+        e = ctypes.c_double()
+        e0 = ctypes.c_double()
+        self._check(self.lib.ric_energy(self.h, _ptr(T1, s1, "T1"), _ptr(T2, s2, "T2"), ctypes.byref(e),
+                                        ctypes.byref(e0)))
+        return e.value, e0.value
+
+    def ladder(self, tau, R2, precision=RIC_FP64):
+        _, s2 = self.amplitude_shapes()
+        self._check(self.lib.ric_ladder(self.h, _ptr(tau, s2, "tau"), _ptr(R2, s2, "R2"), int(precision)))
+
+    def timings(self):
+        a = ctypes.c_double()
+        b = ctypes.c_double()
+        self._check(self.lib.ric_last_timings(self.h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+
+def masks(nc, na, nv, device):
+    """Boolean masks of the stored amplitudes (all-active blocks excluded)."""
+    nH, nP = nc + na, na + nv
+    m1 = torch.ones((nH, nP), dtype=torch.bool, device=device)
+    m1[nc:, :na] = False
+    m2 = torch.ones((nH, nH, nP, nP), dtype=torch.bool, device=device)
+    m2[nc:, nc:, :na, :na] = False
+    return m1, m2
+
+
+def solve(ctx: Context, s, tol=1e-8, max_iter=200, precision=RIC_FP64, polish_tol=None, T1=None, T2=None,
+          log=None):
+    """Regularized Jacobi iteration from T = 0 until ||t_new - t||_2 < tol.
+
+    precision=RIC_FP32MIX: iterate with mixed-precision residuals until the step
+    falls below polish_tol (default 1e-6) or stalls, then continue in fp64 to tol.
+    Returns (E_corr, E0, T1, T2, iterations).
+    """
+    s1, s2 = ctx.amplitude_shapes()
+    dev = ctx.device
+    if T1 is None:
+        T1 = torch.zeros(s1, dtype=torch.float64, device=dev)
+        T2 = torch.zeros(s2, dtype=torch.float64, device=dev)
+    R1 = torch.empty_like(T1)
+    R2 = torch.empty_like(T2)
+    mode = precision
+    switch = polish_tol if polish_tol is not None else 1e-6
+    prev = None
+    for it in range(1, max_iter + 1):
+        ctx.residual(T1, T2, R1, R2, mode)
+        step = ctx.update(T1, T2, R1, R2, s) ** 0.5
+        if log is not None:
+            log.append({"iter": it, "step": step, "precision": "fp32mix" if mode == RIC_FP32MIX else "fp64"})
+        if mode == RIC_FP32MIX and (step < switch or (prev is not None and step > 0.9 * prev)):
+            mode = RIC_FP64
+        elif mode == RIC_FP64 and step < tol:
+            e, e0 = ctx.energy(T1, T2)
+            return e, e0, T1, T2, it
+        prev = step
+    raise RicError(-5, "regularized iteration did not converge")

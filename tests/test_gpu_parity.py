@@ -1,0 +1,157 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle.
+
+Bar: fp64 residuals within 1e-10 relative (max |diff| / max(1, max |oracle|)),
+energies within 1e-9 E_h; integer/structural properties exact.
+"""
+import numpy as np
+import pytest
+
+import synthetic as S
+from oracle import ricmrcc as R
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-10
+ETOL = 1e-9
+
+
+def _ctx(cfg, inp):
+    from paper_2511_03567_amd import ric
+    dev = torch.device("cuda", 0)
+    ctx = ric.Context(0)
+    ctx.set_spaces(cfg.nc, cfg.na, cfg.nv, cfg.naux)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    ctx.load_fock(t(inp.f))
+    ctx.load_df(t(inp.B))
+    if cfg.na:
+        ctx.load_rdms(t(inp.G1), t(inp.G2), t(inp.G3))
+    else:
+        ctx.load_rdms(None, None, None)
+    return ctx, t
+
+
+def _amps(cfg, seed, scale=0.05):
+    rng = np.random.default_rng(seed)
+    nH, nP = cfg.nc + cfg.na, cfg.na + cfg.nv
+    m1, m2 = R.block_mask(cfg.nc, cfg.na, cfg.nv)
+    T1 = rng.standard_normal((nH, nP)) * scale * m1
+    T2 = rng.standard_normal((nH, nH, nP, nP)) * scale
+    T2 = 0.5 * (T2 + T2.transpose(1, 0, 3, 2)) * m2
+    return T1, T2
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(1.0, np.abs(b).max())) if b.size else 0.0
+
+
+CASES = [
+    ("tiny CAS(4,4) nc2 nv10 naux48", S.CONFIGS["tiny_cas44"]),
+    ("CAS(4,4) nc3 nv20 naux30", S.custom_config("c3", 3, 4, 20, 30, 7)),
+    ("single reference nc4 nv9 naux20", S.custom_config("sr", 4, 0, 9, 20, 8)),
+    ("no core CAS(2,2) nv7 naux15", S.custom_config("nocore", 0, 2, 7, 15, 9)),
+    ("CAS(6,6) nc2 nv11 naux25", S.custom_config("cas66", 2, 6, 11, 25, 10)),
+]
+
+
+@pytest.mark.parametrize("name,cfg", CASES, ids=[c[0] for c in CASES])
+def test_residual_energy_match_oracle(name, cfg):
+    print(f"case {name}", flush=True)
+    inp = S.make_inputs(cfg)
+    ctx, t = _ctx(cfg, inp)
+    T1, T2 = _amps(cfg, 3)
+    nH, nP = cfg.nc + cfg.na, cfg.na + cfg.nv
+    R1 = torch.full((nH, nP), 7.0, dtype=torch.float64, device="cuda")
+    R2 = torch.full((nH, nH, nP, nP), 7.0, dtype=torch.float64, device="cuda")
+    ctx.residual(t(T1), t(T2), R1, R2)
+    e, e0 = ctx.energy(t(T1), t(T2))
+    ref = R.Reference(cfg.nc, cfg.na, cfg.nv, inp.f, inp.B, inp.G1, inp.G2, inp.G3)
+    r1, r2 = ref.residual(T1, T2)
+    assert _rel(R1.cpu().numpy(), r1) < RTOL
+    assert _rel(R2.cpu().numpy(), r2) < RTOL
+    assert abs(e - ref.energy(T1, T2)) < ETOL
+    assert abs(e0 - ref.reference_energy()) < ETOL
+    # the excluded all-active blocks are exactly zero; pair symmetry holds exactly
+    g2 = R2.cpu().numpy()
+    assert np.all(g2[cfg.nc:, cfg.nc:, :cfg.na, :cfg.na] == 0.0)
+    assert np.array_equal(g2, g2.transpose(1, 0, 3, 2))
+
+
+@pytest.mark.slow
+def test_residual_matches_oracle_multi_tile():
+    """nH*nP = 640 rows: ring contractions span several 128-wide tiles with a ragged tail."""
+    cfg = S.custom_config("mt", 6, 4, 60, 80, 11)
+    inp = S.make_inputs(cfg)
+    ctx, t = _ctx(cfg, inp)
+    T1, T2 = _amps(cfg, 4, 0.03)
+    nH, nP = cfg.nc + cfg.na, cfg.na + cfg.nv
+    R1 = torch.zeros((nH, nP), dtype=torch.float64, device="cuda")
+    R2 = torch.zeros((nH, nH, nP, nP), dtype=torch.float64, device="cuda")
+    ctx.residual(t(T1), t(T2), R1, R2)
+    ref = R.Reference(cfg.nc, cfg.na, cfg.nv, inp.f, inp.B, inp.G1, inp.G2, inp.G3)
+    r1, r2 = ref.residual(T1, T2)
+    assert _rel(R1.cpu().numpy(), r1) < RTOL
+    assert _rel(R2.cpu().numpy(), r2) < RTOL
+
+
+def test_update_matches_oracle():
+    cfg = S.custom_config("upd", 3, 4, 20, 30, 12)
+    inp = S.make_inputs(cfg)
+    ctx, t = _ctx(cfg, inp)
+    T1, T2 = _amps(cfg, 5)
+    rng = np.random.default_rng(6)
+    m1, m2 = R.block_mask(cfg.nc, cfg.na, cfg.nv)
+    r1 = rng.standard_normal(T1.shape) * m1
+    r2 = rng.standard_normal(T2.shape)
+    r2 = 0.5 * (r2 + r2.transpose(1, 0, 3, 2)) * m2
+    gT1, gT2 = t(T1), t(T2)
+    n2 = ctx.update(gT1, gT2, t(r1), t(r2), 0.5)
+    D1, D2 = R.denominators(inp.f, cfg.nc, cfg.na, cfg.nv)
+    N1 = R.ric_update(T1, r1, D1, 0.5) * m1
+    N2 = R.ric_update(T2, r2, D2, 0.5) * m2
+    assert _rel(gT1.cpu().numpy(), N1) < 1e-14
+    assert _rel(gT2.cpu().numpy(), N2) < 1e-14
+    want = float(np.sum((N1 - T1) ** 2) + np.sum((N2 - T2) ** 2))
+    assert abs(n2 - want) <= 1e-12 * want
+
+
+def _ladder_sample(B, tau, nc, idx):
+    """(ce|df) tau[k,l,e,f] for sampled (k,l,c,d), one element at a time."""
+    Bp = B[:, nc:, nc:]
+    out = []
+    for k, l, c, d in idx:
+        X = np.einsum("xe,klef->xf", Bp[:, c, :], tau[k:k + 1, l:l + 1]) if False else None
+        v = np.einsum("xe,xf,ef->", Bp[:, c, :], Bp[:, d, :], tau[k, l], optimize=True)
+        out.append(v)
+    return np.array(out)
+
+
+@pytest.mark.parametrize("nc,na,nv,naux", [(5, 8, 193, 150), (1, 2, 3, 7)])
+def test_ladder_matches_sampled_definition(nc, na, nv, naux):
+    """R2 += sum_ef (ce|df) tau[k,l,e,f], nP = 201: several W and tau tiles with ragged tails."""
+    print(f"ladder nc={nc} na={na} nv={nv} naux={naux}", flush=True)
+    cfg = S.custom_config("lad", nc, na, nv, naux, 13, ci_fraction=1.0)
+    rng = np.random.default_rng(13)
+    n = nc + na + nv
+    f = np.diag(np.arange(n, dtype=float))
+    B = S.make_df(rng, n, naux)
+    from paper_2511_03567_amd import ric
+    ctx = ric.Context(0)
+    ctx.set_spaces(nc, na, nv, naux)
+    dev = torch.device("cuda", 0)
+    ctx.load_fock(torch.from_numpy(f).to(dev))
+    ctx.load_df(torch.from_numpy(B).to(dev))
+    nH, nP = nc + na, na + nv
+    tau = rng.standard_normal((nH, nH, nP, nP))
+    tau = tau + tau.transpose(1, 0, 3, 2)
+    R2 = torch.zeros((nH, nH, nP, nP), dtype=torch.float64, device=dev)
+    ctx.ladder(torch.from_numpy(tau).to(dev), R2)
+    got = R2.cpu().numpy()
+    idx = [tuple(int(x) for x in (rng.integers(nH), rng.integers(nH), rng.integers(nP), rng.integers(nP)))
+           for _ in range(64)]
+    idx += [(0, 0, 0, 0), (nH - 1, nH - 1, nP - 1, nP - 1), (0, nH - 1, nP - 1, 0)]
+    want = _ladder_sample(B, tau, nc, idx)
+    g = np.array([got[i] for i in idx])
+    assert np.abs(g - want).max() / max(1.0, np.abs(want).max()) < RTOL
+    assert np.array_equal(got, got.transpose(1, 0, 3, 2))
