@@ -24,4 +24,7 @@ hipError_t gemm_nt_f32(const GemmArgs& g, const float* A, const float* B, hipStr
 // fp32 operands and fp32 result (fp64 accumulation inside the tile); no split-K
 hipError_t gemm_nt_f32_out32(const GemmArgs& g, const float* A, const float* B, float* C, hipStream_t st);
 
+// select the tile geometry (0: 128x128x16, 1: 128x128x32, 2: 256x128x16, 3: 256x256x16); -1 default
+void gemm_set_variant(int v);
+
 }  // namespace ric

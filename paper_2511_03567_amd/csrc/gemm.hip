@@ -28,46 +28,10 @@ namespace ric {
 
 namespace {
 
-constexpr int BM = 128;
-constexpr int BN = 128;
-constexpr int BK = 16;
-constexpr int LDSK = BK + 1;      // padded row (in elements) of the K-contiguous LDS tiles
-
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
-
-template <typename T>
-struct Slab {
-  T a[8];
-  T b[8];
-};
-
-template <typename T>
-__device__ inline void fetch(const T* __restrict__ A, const T* __restrict__ B, long lda, long ldb,
-                             int M, int N, int K, int m0, int n0, int k0, int tid, Slab<T>& s) {
-  // 256 threads load a 128 x 16 slab of A and of B: thread -> (row = tid / 2, 8 consecutive k)
-  const int r = tid >> 1;
-  const int kk = (tid & 1) * 8;
-  const int gm = m0 + r;
-  const int gn = n0 + r;
-#pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    const int gk = k0 + kk + j;
-    s.a[j] = (gm < M && gk < K) ? A[(long)gm * lda + gk] : T(0);
-    s.b[j] = (gn < N && gk < K) ? B[(long)gn * ldb + gk] : T(0);
-  }
-}
-
-template <typename T>
-__device__ inline void stash(T* As, T* Bs, int tid, const Slab<T>& s) {
-  const int r = tid >> 1;
-  const int kk = (tid & 1) * 8;
-#pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    As[r * LDSK + kk + j] = s.a[j];
-    Bs[r * LDSK + kk + j] = s.b[j];
-  }
-}
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f4v __attribute__((ext_vector_type(4)));
 
 __device__ inline void mma(d4& c, double a, double b) {
   c = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -77,30 +41,145 @@ __device__ inline void mma(f4& c, float a, float b) {
   c = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// Geometry of one kernel instance: BM x BN tile, K slab BK, WM x WN wavefronts of
+// 64 x 64 (4 x 4 MFMA tiles of 16 x 16 each).
+template <int BM_, int BN_, int BK_, int WM_, int WN_, int MINB_ = 1>
+struct Geo {
+  static constexpr int BM = BM_, BN = BN_, BK = BK_, WM = WM_, WN = WN_, MINB = MINB_;
+  static constexpr int NT = 64 * WM * WN;
+  static constexpr int LDSK = BK + 1;           // padded LDS row (elements)
+  static constexpr int KPT = BK < 8 ? BK : 8;   // consecutive k per thread per load
+  static constexpr int TPR = BK / KPT;          // threads per row
+  static constexpr int RPP = NT / TPR;          // rows per pass
+  static constexpr int PA = (BM + RPP - 1) / RPP;
+  static constexpr int PB = (BN + RPP - 1) / RPP;
+};
+
+template <typename T, typename Gm>
+struct Slab {
+  T a[Gm::PA][Gm::KPT];
+  T b[Gm::PB][Gm::KPT];
+};
+
+// VEC: rows of A/B are 16-byte aligned and K is a multiple of the vector width,
+// so each thread's run of KPT values is fetched with 16-byte loads.
+template <typename T, typename Gm, bool VEC>
+__device__ inline void fetch(const T* __restrict__ A, const T* __restrict__ B, long lda, long ldb, int M, int N,
+                             int K, int m0, int n0, int k0, int tid, Slab<T, Gm>& s) {
+  const int r = tid / Gm::TPR;
+  const int kk = (tid % Gm::TPR) * Gm::KPT;
+  constexpr int VW = 16 / sizeof(T);
+#pragma unroll
+  for (int p = 0; p < Gm::PA; ++p) {
+    const int row = r + p * Gm::RPP;
+    const int gm = m0 + row;
+    const bool okr = row < Gm::BM && gm < M;
+    if constexpr (VEC) {
+#pragma unroll
+      for (int j = 0; j < Gm::KPT; j += VW) {
+        const int gk = k0 + kk + j;
+        if (okr && gk < K) {
+          if constexpr (sizeof(T) == 8) {
+            const d2v v = *reinterpret_cast<const d2v*>(A + (long)gm * lda + gk);
+            s.a[p][j] = v[0];
+            s.a[p][j + 1] = v[1];
+          } else {
+            const f4v v = *reinterpret_cast<const f4v*>(A + (long)gm * lda + gk);
+            s.a[p][j] = v[0]; s.a[p][j + 1] = v[1]; s.a[p][j + 2] = v[2]; s.a[p][j + 3] = v[3];
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < VW; ++q) s.a[p][j + q] = T(0);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < Gm::KPT; ++j) {
+        const int gk = k0 + kk + j;
+        s.a[p][j] = (okr && gk < K) ? A[(long)gm * lda + gk] : T(0);
+      }
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < Gm::PB; ++p) {
+    const int row = r + p * Gm::RPP;
+    const int gn = n0 + row;
+    const bool okr = row < Gm::BN && gn < N;
+    if constexpr (VEC) {
+#pragma unroll
+      for (int j = 0; j < Gm::KPT; j += VW) {
+        const int gk = k0 + kk + j;
+        if (okr && gk < K) {
+          if constexpr (sizeof(T) == 8) {
+            const d2v v = *reinterpret_cast<const d2v*>(B + (long)gn * ldb + gk);
+            s.b[p][j] = v[0];
+            s.b[p][j + 1] = v[1];
+          } else {
+            const f4v v = *reinterpret_cast<const f4v*>(B + (long)gn * ldb + gk);
+            s.b[p][j] = v[0]; s.b[p][j + 1] = v[1]; s.b[p][j + 2] = v[2]; s.b[p][j + 3] = v[3];
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < VW; ++q) s.b[p][j + q] = T(0);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < Gm::KPT; ++j) {
+        const int gk = k0 + kk + j;
+        s.b[p][j] = (okr && gk < K) ? B[(long)gn * ldb + gk] : T(0);
+      }
+    }
+  }
+}
+
+template <typename T, typename Gm>
+__device__ inline void stash(T* As, T* Bs, int tid, const Slab<T, Gm>& s) {
+  const int r = tid / Gm::TPR;
+  const int kk = (tid % Gm::TPR) * Gm::KPT;
+#pragma unroll
+  for (int p = 0; p < Gm::PA; ++p) {
+    const int row = r + p * Gm::RPP;
+    if (row < Gm::BM) {
+#pragma unroll
+      for (int j = 0; j < Gm::KPT; ++j) As[row * Gm::LDSK + kk + j] = s.a[p][j];
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < Gm::PB; ++p) {
+    const int row = r + p * Gm::RPP;
+    if (row < Gm::BN) {
+#pragma unroll
+      for (int j = 0; j < Gm::KPT; ++j) Bs[row * Gm::LDSK + kk + j] = s.b[p][j];
+    }
+  }
+}
+
 // Tile kernel.  Acc is the MFMA accumulator type; for fp32 operands the
 // per-slab fp32 result is added into fp64 registers (acc64).
-template <typename T, typename Acc, typename TC>
-__global__ void __launch_bounds__(256)
+template <typename T, typename Acc, typename TC, typename Gm, bool VEC>
+__global__ void __launch_bounds__(Gm::NT, Gm::MINB)
 gemm_nt_kernel(int M, int N, int K, double alpha, const T* __restrict__ A, long lda,
                const T* __restrict__ B, long ldb, double beta, TC* __restrict__ C, long ldc,
                long strideA, long strideB, long strideC, int zdiv, int ksplit, long strideP,
                double* __restrict__ partial) {
+  constexpr int BM = Gm::BM, BN = Gm::BN, BK = Gm::BK, LDSK = Gm::LDSK;
   __shared__ T As[2][BM * LDSK];
   __shared__ T Bs[2][BN * LDSK];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wm = (wave >> 1) * 64;
-  const int wn = (wave & 1) * 64;
+  const int wm = (wave / Gm::WN) * 64;
+  const int wn = (wave % Gm::WN) * 64;
   // batch: z -> (z / zdiv) selects A, (z % zdiv) selects B, z selects C
   const int zb = blockIdx.z / ksplit;
   const int ks = blockIdx.z % ksplit;
   A += (long)(zb / zdiv) * strideA;
   B += (long)(zb % zdiv) * strideB;
   C += (long)zb * strideC;
-  // XCD-aware tile order: consecutive workgroup ids land on different XCDs, so
-  // walk the tile grid in column-major groups to keep neighbouring tiles of A/B
-  // resident in the same L2.
+  // XCD-aware tile order: consecutive workgroup ids land on different XCDs
+  // (round robin over 8), so give each XCD a contiguous run of tiles that walks
+  // down M with a fixed N column and keeps that B tile hot in the XCD's L2.
   const int tiles_m = (M + BM - 1) / BM;
   const int nx = gridDim.x;
   const int lin = (nx % 8 == 0) ? (int)(blockIdx.x % 8) * (nx / 8) + (int)(blockIdx.x / 8) : (int)blockIdx.x;
@@ -125,18 +204,18 @@ gemm_nt_kernel(int M, int N, int K, double alpha, const T* __restrict__ A, long 
       }
     }
 
-  Slab<T> s;
+  Slab<T, Gm> s;
   int buf = 0;
   if (kbeg < kend) {
-    fetch(A, B, lda, ldb, M, N, kend, m0, n0, kbeg, tid, s);
-    stash(As[0], Bs[0], tid, s);
+    fetch<T, Gm, VEC>(A, B, lda, ldb, M, N, kend, m0, n0, kbeg, tid, s);
+    stash<T, Gm>(As[0], Bs[0], tid, s);
   }
   __syncthreads();
   const int row = lane & 15;
   const int kq = lane >> 4;
   for (int k0 = kbeg; k0 < kend; k0 += BK) {
     const bool more = k0 + BK < kend;
-    if (more) fetch(A, B, lda, ldb, M, N, kend, m0, n0, k0 + BK, tid, s);
+    if (more) fetch<T, Gm, VEC>(A, B, lda, ldb, M, N, kend, m0, n0, k0 + BK, tid, s);
     const T* as = As[buf];
     const T* bs = Bs[buf];
 #pragma unroll
@@ -163,7 +242,7 @@ gemm_nt_kernel(int M, int N, int K, double alpha, const T* __restrict__ A, long 
         }
     }
     if (more) {
-      stash(As[buf ^ 1], Bs[buf ^ 1], tid, s);
+      stash<T, Gm>(As[buf ^ 1], Bs[buf ^ 1], tid, s);
       buf ^= 1;
     }
     __syncthreads();
@@ -196,6 +275,8 @@ gemm_nt_kernel(int M, int N, int K, double alpha, const T* __restrict__ A, long 
       }
 }
 
+int g_variant = -1;  // -1: default geometry; >= 0 forces one (benchmarking)
+
 // Sum of split-K partial tiles in a fixed order (deterministic), then alpha/beta.
 __global__ void splitk_reduce(int M, int N, int ksplit, int batches, double alpha, double beta,
                               const double* __restrict__ partial, long strideP, double* __restrict__ C,
@@ -213,10 +294,10 @@ __global__ void splitk_reduce(int M, int N, int ksplit, int batches, double alph
   }
 }
 
-template <typename T, typename Acc, typename TC>
-hipError_t launch(const GemmArgs& g, const T* A, const T* B, TC* C, hipStream_t st, double* scratch,
-                  size_t scratch_elems) {
-  if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
+template <typename T, typename Acc, typename TC, typename Gm>
+hipError_t launch_geo(const GemmArgs& g, const T* A, const T* B, TC* C, hipStream_t st, double* scratch,
+                      size_t scratch_elems) {
+  constexpr int BM = Gm::BM, BN = Gm::BN;
   const int tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
   int ksplit = 1;
   if (g.K > 0) {
@@ -225,18 +306,22 @@ hipError_t launch(const GemmArgs& g, const T* A, const T* B, TC* C, hipStream_t 
     while (ksplit > 1 && (size_t)ksplit * g.batch * g.M * g.N > scratch_elems) ksplit /= 2;
     if (sizeof(TC) != sizeof(double)) ksplit = 1;
   }
-  if (g.K <= 0) {
-    // C = beta * C
-    if (g.beta == 1.0) return hipSuccess;
-    ksplit = 1;
-  }
   while (ksplit > 1 && (long)g.batch * ksplit > 65535) ksplit /= 2;
   if ((long)g.batch * ksplit > 65535) return hipErrorInvalidValue;
+  constexpr int VW = 16 / sizeof(T);
+  const bool vec = (g.K % VW == 0) && (g.lda % VW == 0) && (g.ldb % VW == 0) &&
+                   ((uintptr_t)A % 16 == 0) && ((uintptr_t)B % 16 == 0) && (g.strideA % VW == 0) &&
+                   (g.strideB % VW == 0);
   dim3 grid(tiles, 1, g.batch * ksplit);
   const long strideP = (long)g.M * g.N;
-  hipLaunchKernelGGL((gemm_nt_kernel<T, Acc, TC>), grid, dim3(256), 0, st, g.M, g.N, g.K, g.alpha, A, g.lda,
-                     B, g.ldb, g.beta, C, g.ldc, g.strideA, g.strideB, g.strideC, g.zdiv, ksplit,
-                     strideP, scratch);
+  if (vec)
+    hipLaunchKernelGGL((gemm_nt_kernel<T, Acc, TC, Gm, true>), grid, dim3(Gm::NT), 0, st, g.M, g.N, g.K, g.alpha, A,
+                       g.lda, B, g.ldb, g.beta, C, g.ldc, g.strideA, g.strideB, g.strideC, g.zdiv, ksplit, strideP,
+                       scratch);
+  else
+    hipLaunchKernelGGL((gemm_nt_kernel<T, Acc, TC, Gm, false>), grid, dim3(Gm::NT), 0, st, g.M, g.N, g.K, g.alpha, A,
+                       g.lda, B, g.ldb, g.beta, C, g.ldc, g.strideA, g.strideB, g.strideC, g.zdiv, ksplit, strideP,
+                       scratch);
   if (ksplit > 1) {
     const long total = (long)g.batch * g.M * g.N;
     const int nb = (int)std::min<long>((total + 255) / 256, 65536);
@@ -244,6 +329,31 @@ hipError_t launch(const GemmArgs& g, const T* A, const T* B, TC* C, hipStream_t 
                        g.beta, scratch, strideP, reinterpret_cast<double*>(C), g.ldc, g.strideC);
   }
   return hipGetLastError();
+}
+
+using G128x16 = Geo<128, 128, 16, 2, 2>;
+using G128x32 = Geo<128, 128, 32, 2, 2>;
+using G256x16 = Geo<256, 128, 16, 4, 2>;
+using G256sq = Geo<256, 256, 16, 4, 4>;
+using G128x16b2 = Geo<128, 128, 16, 2, 2, 2>;
+using G128x32b2 = Geo<128, 128, 32, 2, 2, 2>;
+
+template <typename T, typename Acc, typename TC>
+hipError_t launch(const GemmArgs& g, const T* A, const T* B, TC* C, hipStream_t st, double* scratch,
+                  size_t scratch_elems) {
+  if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
+  if (g.K <= 0 && g.beta == 1.0) return hipSuccess;
+  int v = g_variant;
+  // measured on gfx950: fp64 best with 128x128x16 tiles at two workgroups per CU,
+  // fp32 with 128x128x32 tiles
+  if (v < 0) v = sizeof(T) == 8 ? 3 : 1;
+  switch (v) {
+    case 1: return launch_geo<T, Acc, TC, G128x32>(g, A, B, C, st, scratch, scratch_elems);
+    case 2: return launch_geo<T, Acc, TC, G256x16>(g, A, B, C, st, scratch, scratch_elems);
+    case 3: return launch_geo<T, Acc, TC, G128x16b2>(g, A, B, C, st, scratch, scratch_elems);
+    case 4: return launch_geo<T, Acc, TC, G128x32b2>(g, A, B, C, st, scratch, scratch_elems);
+    default: return launch_geo<T, Acc, TC, G128x16>(g, A, B, C, st, scratch, scratch_elems);
+  }
 }
 
 }  // namespace
@@ -261,5 +371,7 @@ hipError_t gemm_nt_f32(const GemmArgs& g, const float* A, const float* B, hipStr
 hipError_t gemm_nt_f32_out32(const GemmArgs& g, const float* A, const float* B, float* C, hipStream_t st) {
   return launch<float, f4, float>(g, A, B, C, st, nullptr, 0);
 }
+
+void gemm_set_variant(int v) { g_variant = v; }
 
 }  // namespace ric

@@ -340,6 +340,13 @@ hipError_t strided_copy_f32(const Iter& it, double alpha, const double* in, floa
   return hipGetLastError();
 }
 
+hipError_t strided_copy_f32f32(const Iter& it, const float* in, float* out, hipStream_t st) {
+  if (it.total <= 0) return hipSuccess;
+  hipLaunchKernelGGL((strided_axpby<float, float>), dim3(blocks_for(it.total)), dim3(kThreads), 0, st, it, 1.0,
+                     in, 0.0, out);
+  return hipGetLastError();
+}
+
 hipError_t fill(double* p, long n, double v, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(fill_kernel, dim3(blocks_for(n)), dim3(kThreads), 0, st, p, n, v);

@@ -5,8 +5,10 @@
 #include <dlfcn.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <fstream>
 #include <functional>
@@ -199,7 +201,7 @@ struct ric_ctx {
 
   // owned device tensors
   DevBuf f, eps, B, BT, BT32, g1, g2, g3, ga, ea, l2, k2, l3, k3, I4, I3, IJ, IK, tau, Edev, red, e0;
-  DevBuf scrA, scrB, scrC, scrK, wbuf, lad32, dfa, dfb;
+  DevBuf scrA, scrB, scrC, scrK, wbuf, wbuf2, lad32, dfa, dfb;
   Pool pool;
   int precision = RIC_FP64;
   double ladder_ms = 0.0, total_ms = 0.0;
@@ -208,7 +210,7 @@ struct ric_ctx {
 
   ~ric_ctx() {
     for (DevBuf* b : {&f, &eps, &B, &BT, &BT32, &g1, &g2, &g3, &ga, &ea, &l2, &k2, &l3, &k3, &I4, &I3, &IJ, &IK,
-                      &tau, &Edev, &red, &e0, &scrA, &scrB, &scrC, &scrK, &wbuf, &lad32, &dfa, &dfb})
+                      &tau, &Edev, &red, &e0, &scrA, &scrB, &scrC, &scrK, &wbuf, &wbuf2, &lad32, &dfa, &dfb})
       b->release();
     pool.release();
     for (auto& e : ev)
@@ -631,37 +633,43 @@ struct ric_ctx {
       HIPCHK(ric::strided_copy_f32(it, 1.0, taup, reinterpret_cast<float*>(lad32.p), stream));
       tau32 = reinterpret_cast<const float*>(lad32.p);
     }
-    // chunk of c rows: W[(c - c0), d, e, f] for d < c1
-    const double budget = 1.6e9;  // elements of W per chunk
+    // chunk of c rows.  W'[(c,e)][(d,f)] = sum_X BT[c][e][X] BT[d][f][X] for d < c1 is one
+    // large GEMM (M = rows*nP, N = c1*nP, K = naux); it is then permuted to
+    // W[(c,d)][(e,f)] so that (e,f) is the contiguous contraction index.
+    const double budget = 1.4e9;  // elements of W per chunk (two buffers)
     long chunk = std::max<long>(1, (long)(budget / ((double)np_ * pp)));
     chunk = std::min<long>(chunk, np_);
     const size_t welems = (size_t)chunk * np_ * pp;
     wbuf.ensure(mixed ? (welems + 1) / 2 : welems);
+    wbuf2.ensure(mixed ? (welems + 1) / 2 : welems);
     scrC.ensure((size_t)nh * nh * chunk * np_);
     scrK.ensure(64L * 1024 * 1024);
     for (int c0 = 0; c0 < np_; c0 += (int)chunk) {
       const int c1 = std::min<int>(np_, c0 + (int)chunk);
       const int rows = c1 - c0;
-      // W build: batch z = (c - c0) * c1 + d
       GemmArgs g;
-      g.M = np_;
-      g.N = np_;
+      g.M = rows * np_;
+      g.N = c1 * np_;
       g.K = nx;
       g.lda = nx;
       g.ldb = nx;
-      g.ldc = np_;
-      g.batch = rows * c1;
-      g.zdiv = c1;
-      g.strideA = (long)np_ * nx;
-      g.strideB = (long)np_ * nx;
-      g.strideC = pp;
+      g.ldc = (long)c1 * np_;
+      Iter it;  // W[c][d][e][f] <- W'[c][e][d][f]
+      it.nd = 4;
+      it.ext[0] = rows; it.ext[1] = c1; it.ext[2] = np_; it.ext[3] = np_;
+      it.so[0] = (long)c1 * pp; it.so[1] = pp; it.so[2] = np_; it.so[3] = 1;
+      it.si[0] = (long)np_ * c1 * np_; it.si[1] = np_; it.si[2] = (long)c1 * np_; it.si[3] = 1;
+      it.total = (long)rows * c1 * pp;
       if (!mixed) {
-        g.C = wbuf.p;
+        g.C = wbuf2.p;
         HIPCHK(ric::gemm_nt_f64(g, BT.p + (long)c0 * np_ * nx, BT.p, stream, scrK.p, scrK.n));
+        HIPCHK(ric::strided_copy(it, 1.0, wbuf2.p, 0.0, wbuf.p, stream));
       } else {
         HIPCHK(ric::gemm_nt_f32_out32(g, reinterpret_cast<const float*>(BT32.p) + (long)c0 * np_ * nx,
-                                      reinterpret_cast<const float*>(BT32.p), reinterpret_cast<float*>(wbuf.p),
+                                      reinterpret_cast<const float*>(BT32.p), reinterpret_cast<float*>(wbuf2.p),
                                       stream));
+        HIPCHK(ric::strided_copy_f32f32(it, reinterpret_cast<const float*>(wbuf2.p),
+                                        reinterpret_cast<float*>(wbuf.p), stream));
       }
       // contraction: C[kl][(c - c0) * c1 + d] = sum_ef tau[kl][ef] W[(c,d)][ef]
       GemmArgs h;
@@ -682,8 +690,45 @@ struct ric_ctx {
   }
 
   // -- plan execution -----------------------------------------------------------------------
-  void run(std::vector<Op>& ops) {
+  // RIC_PROFILE=1: per-operation-kind device time (synchronizes after every operation)
+  bool profile = getenv("RIC_PROFILE") != nullptr;
+  std::map<std::string, std::pair<double, long>> prof;
+
+  // RIC_PROGRESS=1: one stderr line when each expensive phase of a plan section ends
+  bool progress = getenv("RIC_PROGRESS") != nullptr;
+  bool warmed = false;
+
+  // populate the intermediate pool with every size the plan allocates (no kernels)
+  void warm_pool(std::vector<Op>& ops) {
     for (Op& op : ops) {
+      if (op.kind == K_ALLOC) {
+        slots[op.slot].decl = op.decl;
+        slots[op.slot].ptr = pool.get((size_t)slot_elems(op.slot));
+      } else if (op.kind == K_FREE) {
+        pool.put(slots[op.slot].ptr, (size_t)slot_elems(op.slot));
+        slots[op.slot].ptr = nullptr;
+      }
+    }
+  }
+
+  void run(std::vector<Op>& ops) {
+    if (!warmed) {
+      warm_pool(residual_ops);
+      warm_pool(energy_ops);
+      warmed = true;
+    }
+    hipEvent_t pa = nullptr, pb = nullptr;
+    auto t_start = std::chrono::steady_clock::now();
+    double flops_done = 0.0;
+    int big_done = 0;
+    if (profile) {
+      HIPCHK(hipEventCreate(&pa));
+      HIPCHK(hipEventCreate(&pb));
+    }
+    static const char* kname[] = {"ZERO", "ALLOC", "FREE", "CONTRACT", "CONTRACT0", "ADD", "DFC", "SYMM",
+                                  "LADDER", "MASK"};
+    for (Op& op : ops) {
+      if (profile) HIPCHK(hipEventRecord(pa, stream));
       switch (op.kind) {
         case K_ALLOC: {
           Slot& s = slots[op.slot];
@@ -726,7 +771,56 @@ struct ric_ctx {
           HIPCHK(ric::mask_active(slots[slot_of["R1"]].ptr, slots[slot_of["R2"]].ptr, sz.nc, sz.na, sz.nv, stream));
           break;
       }
+      if (progress && (op.kind == K_LADDER || op.kind == K_DFC ||
+                       ((op.kind == K_CONTRACT || op.kind == K_CONTRACT0) && op_flops(op) > 5e13))) {
+        // report after the operation has finished on the device
+        HIPCHK(hipStreamSynchronize(stream));
+        ++big_done;
+        const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+        if (op.kind == K_LADDER || big_done % 16 == 0)
+          fprintf(stderr, "  [ric] %s done: %d large operations, %.1f s\n", kind_name(op.kind), big_done, el);
+      }
+      if (profile) {
+        HIPCHK(hipEventRecord(pb, stream));
+        HIPCHK(hipEventSynchronize(pb));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, pa, pb));
+        std::string key = kname[op.kind];
+        if (op.kind == K_CONTRACT || op.kind == K_CONTRACT0 || op.kind == K_DFC) {
+          long big = 0;
+          for (auto& o : op.o) {
+            long e = 1;
+            for (Rng r : o.sub) e *= sz.ext(r);
+            big = std::max(big, e);
+          }
+          key += big > 100000000L ? "/big" : big > 1000000L ? "/mid" : "/small";
+        }
+        auto& pr = prof[key];
+        pr.first += ms;
+        pr.second += 1;
+      }
     }
+    if (profile) {
+      for (auto& kv : prof) fprintf(stderr, "  RIC_PROFILE %-16s %10.3f ms  %6ld ops\n", kv.first.c_str(), kv.second.first,
+                                    kv.second.second);
+      prof.clear();
+      (void)hipEventDestroy(pa);
+      (void)hipEventDestroy(pb);
+    }
+  }
+
+  static const char* kind_name(Kind k) {
+    static const char* n[] = {"ZERO", "ALLOC", "FREE", "CONTRACT", "CONTRACT0", "ADD", "DFC", "SYMM", "LADDER", "MASK"};
+    return n[k];
+  }
+
+  double op_flops(const Op& op) const {
+    std::map<int, long> ext;
+    for (const auto& o : op.o)
+      for (size_t i = 0; i < o.lab.size(); ++i) ext[o.lab[i]] = sz.ext(o.sub[i]);
+    double f = 2.0;
+    for (auto& kv : ext) f *= (double)kv.second;
+    return f;
   }
 
   void bind(const char* name, const double* p) { slots[slot_of.at(name)].ptr = const_cast<double*>(p); }

@@ -56,6 +56,11 @@ def parent(r):
     return H if r in SMALL else P
 
 
+def _widen(r):
+    """Core widens to the hole range, virtual to the particle range; others stay."""
+    return {C: H, V: P}.get(r, r)
+
+
 class Operand:
     __slots__ = ("name", "ranges", "labels", "src")
 
@@ -328,9 +333,13 @@ def compile_plan(e_terms, r1_terms, s2_terms):
                     ren[l] = f"c{cnt}"
                     cnt += 1
             ylabs = sorted(Yop.labels, key=lambda l: ren[l])
-            key = (target, P0.name, P0.ranges, tuple(ren[l] for l in P0.labels),
-                   tuple(out_ranges), tuple((ren[l], rng[l]) for l in ylabs))
-            groups.setdefault(key, []).append((t.coef, ysteps, Yop, ylabs, P0, ext, out_ranges, rng, ren))
+            # group on parent ranges: every label except the outputs carried by P0 is
+            # widened to H or P; members fill sub-blocks of the shared intermediate
+            p0_ext = set(P0.labels) & set(ext)
+            g_rng = {l: (rng[l] if l in p0_ext else _widen(rng[l])) for l in rng}
+            key = (target, P0.name, tuple(g_rng[l] for l in P0.labels), tuple(ren[l] for l in P0.labels),
+                   tuple(g_rng[l] for l in ext), tuple((ren[l], g_rng[l]) for l in ylabs))
+            groups.setdefault(key, []).append((t.coef, ysteps, Yop, ylabs, P0, ext, out_ranges, rng, ren, g_rng))
         else:
             direct.append((target, t.coef, ext, out_ranges, ops, rng))
 
@@ -426,22 +435,68 @@ def _emit_into(plan, coef, ops, out, rng):
 def _emit_groups(plan, groups):
     for key, members in groups.items():
         target = key[0]
-        coef0, ysteps0, Yop0, ylabs0, P0, ext0, out_ranges0, rng0, ren0 = members[0]
+        coef0, ysteps0, Yop0, ylabs0, P00, ext0, out_ranges0, rng0, ren0, g0 = members[0]
         if len(members) == 1 and not ysteps0:
             # plain product of two stored tensors
             out = Operand(target, out_ranges0, ext0)
-            plan.contract(out, coef0, P0, Yop0)
+            plan.contract(out, coef0, P00, Yop0)
             continue
-        yr = [rng0[l] for l in ylabs0]
+        yr = [g0[l] for l in ylabs0]
         acc = plan.new_tmp(yr)
         plan.lines.append(f"ZERO {acc}")
-        for coef, ysteps, Yop, ylabs, P0m, ext, out_ranges, rng, ren in members:
+        # second level: members whose intermediate is one product X * Z of two stored
+        # tensors with the same X pattern share X; their Z's are summed first
+        sub = OrderedDict()
+        rest_members = []
+        for m in members:
+            coef, ysteps, Yop, ylabs, P0m, ext, out_ranges, rng, ren, g = m
+            if len(ysteps) == 1:
+                a, b, new = ysteps[0]
+                placed = False
+                for X, Z in ((a, b), (b, a)):
+                    if X.name.startswith("t") or Z.name.startswith("t") and Z.name[1:].isdigit():
+                        continue
+                    # roles: labels of Y map to their canonical names in the group
+                    yrole = {l: ren.get(l, None) for l in ylabs}
+                    inner = [l for l in X.labels if l in Z.labels]
+                    iren = {l: f"i{k}" for k, l in enumerate(inner)}
+                    # X keeps the exact ranges of its own Y labels; inner labels widen
+                    xkey = tuple((yrole.get(l) or iren[l], _widen(rng[l]) if l in iren else rng[l])
+                                 for l in X.labels)
+                    zlabs = sorted(Z.labels, key=lambda l: (yrole.get(l) or iren[l]))
+                    zkey = tuple((yrole.get(l) or iren[l], _widen(rng[l])) for l in zlabs)
+                    key2 = (X.name, xkey, zkey)
+                    sub.setdefault(key2, []).append((coef, X, Z, zlabs, rng, ylabs, m))
+                    placed = True
+                    break
+                if placed:
+                    continue
+            rest_members.append(m)
+        for key2, items in sub.items():
+            if len(items) == 1:
+                rest_members.append(items[0][6])
+                continue
+            coef0_, X0, Z0, zl0, rng0_, yl0, m0 = items[0]
+            zr = [_widen(rng0_[l]) for l in zl0]
+            zacc = plan.new_tmp(zr)
+            plan.lines.append(f"ZERO {zacc}")
+            for coef, X, Z, zlabs, rng, ylabs, m in items:
+                plan.add(Operand(zacc, [rng[l] for l in zlabs], zlabs), coef, Z)
+            # X over the ranges of the first member, its inner labels widened like Z
+            xr = [(_widen(r) if (l in zl0 and l not in yl0) else r) for l, r in zip(X0.labels, X0.ranges)]
+            Xop = Operand(X0.name, xr, X0.labels)
+            accop = Operand(acc, [(rng0_[l] if l in X0.labels else _widen(rng0_[l])) for l in yl0], yl0)
+            plan.contract(accop, 1, Xop, Operand(zacc, zr, zl0))
+            plan.free(zacc)
+        for coef, ysteps, Yop, ylabs, P0m, ext, out_ranges, rng, ren, g in rest_members:
+            # the member's own (possibly narrower) ranges address a sub-block of acc
             accop = Operand(acc, [rng[l] for l in ylabs], ylabs)
             if not ysteps:
                 plan.add(accop, coef, Yop)
             else:
                 _emit_steps(plan, ysteps, final_out=accop, alpha=coef)
-        out = Operand(target, out_ranges0, ext0)
+        out = Operand(target, [g0[l] for l in ext0], ext0)
+        P0 = Operand(P00.name, [g0[l] for l in P00.labels], P00.labels)
         plan.contract(out, 1, P0, Operand(acc, yr, ylabs0))
         plan.free(acc)
 
