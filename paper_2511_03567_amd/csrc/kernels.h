@@ -34,6 +34,16 @@ hipError_t prepare_cumulants(const double* g1, const double* g2, const double* g
                              double* l2, double* k2, double* l3, double* k3, hipStream_t st);
 hipError_t reference_energy(const double* f, int n, const double* I4, int nc, int na, const double* g1,
                             const double* g2, double* out, hipStream_t st);
+// pair-packed ladder: tau+/- (k<=l, e>=f / k<l, e>f), W+/- per (c,d) pair, and the scatter to R2
+// rows of the packed operands have leading dimensions ldp (+) and ldm (-), padding zero-filled
+hipError_t pack_tau(const double* tau, int nh, int np, double* tp, double* tm, long ldp, long ldm, hipStream_t st);
+hipError_t pack_tau_f32(const double* tau, int nh, int np, float* tp, float* tm, long ldp, long ldm, hipStream_t st);
+hipError_t pack_w(const double* w, int np, int rows, int c1, double* wp, double* wm, long ldp, long ldm,
+                  hipStream_t st);
+hipError_t pack_w_f32(const float* w, int np, int rows, int c1, float* wp, float* wm, long ldp, long ldm,
+                      hipStream_t st);
+hipError_t ladder_scatter_pm_add(const double* sp, const double* sm, int nh, int np, int c0, int c1, double* r2,
+                                 hipStream_t st);
 hipError_t ladder_scatter_add(const double* C, int nh, int np, int c0, int c1, int ncol, double* r2, hipStream_t st);
 
 }  // namespace ric

@@ -322,6 +322,120 @@ __global__ void ladder_scatter(const double* __restrict__ Cm, int nh, int np, in
   }
 }
 
+// ---- pair-packed ladder (+/- combinations) -----------------------------------------------
+// Packed pair index of (e, f) with e >= f: e (e + 1) / 2 + f; strict e > f: e (e - 1) / 2 + f.
+
+// tau+[kl][ef] = w (tau[k,l,e,f] + tau[k,l,f,e]) / 2 for k <= l, e >= f (w = 1/2 on e == f)
+// tau-[kl][ef] = (tau[k,l,e,f] - tau[k,l,f,e]) / 2       for k <  l, e >  f
+template <typename TO>
+__global__ void pack_tau_kernel(const double* __restrict__ tau, int nh, int np, TO* __restrict__ tp,
+                                TO* __restrict__ tm, long ldp, long ldm) {
+  const long nhp = (long)nh * (nh + 1) / 2, npp = (long)np * (np + 1) / 2;
+  const long nhm = (long)nh * (nh - 1) / 2, npm = (long)np * (np - 1) / 2;
+  const long total = nhp * ldp + nhm * ldm;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
+    const bool plus = t < nhp * ldp;
+    const long u = plus ? t : t - nhp * ldp;
+    const long ld = plus ? ldp : ldm;
+    const long r = u / ld, q = u % ld;
+    if (q >= (plus ? npp : npm)) {  // zero padding of the packed rows
+      if (plus) tp[u] = (TO)0; else tm[u] = (TO)0;
+      continue;
+    }
+    // row r -> (k, l), k <= l (plus) or k < l (minus), enumerated by l
+    int l = (int)((sqrt(8.0 * r + 1.0) - 1.0) / 2.0);
+    if (plus) {
+      while ((long)l * (l + 1) / 2 > r) --l;
+      while ((long)(l + 1) * (l + 2) / 2 <= r) ++l;
+    } else {
+      l = (int)((sqrt(8.0 * r + 1.0) + 1.0) / 2.0);
+      while ((long)l * (l - 1) / 2 > r) --l;
+      while ((long)(l + 1) * l / 2 <= r) ++l;
+    }
+    const int k = plus ? (int)(r - (long)l * (l + 1) / 2) : (int)(r - (long)l * (l - 1) / 2);
+    int e;
+    if (plus) {
+      e = (int)((sqrt(8.0 * q + 1.0) - 1.0) / 2.0);
+      while ((long)e * (e + 1) / 2 > q) --e;
+      while ((long)(e + 1) * (e + 2) / 2 <= q) ++e;
+    } else {
+      e = (int)((sqrt(8.0 * q + 1.0) + 1.0) / 2.0);
+      while ((long)e * (e - 1) / 2 > q) --e;
+      while ((long)(e + 1) * e / 2 <= q) ++e;
+    }
+    const int f = plus ? (int)(q - (long)e * (e + 1) / 2) : (int)(q - (long)e * (e - 1) / 2);
+    const long base = ((long)k * nh + l) * np;
+    const double a = tau[(base + e) * np + f];
+    const double b = tau[(base + f) * np + e];
+    if (plus) tp[u] = (TO)((e == f ? 0.25 : 0.5) * (a + b));
+    else tm[u] = (TO)(0.5 * (a - b));
+  }
+}
+
+// W+[(c,d)][ef] = W'[c][e][d][f] + W'[c][f][d][e] (e >= f), W-[(c,d)][ef] = difference (e > f),
+// for c in [c0, c1), d < c1; W' rows (c, e) of length c1 * np
+template <typename T>
+__global__ void pack_w_kernel(const T* __restrict__ wsrc, int np, int rows, int c1, T* __restrict__ wp,
+                              T* __restrict__ wm, long ldp, long ldm) {
+  const long npp = (long)np * (np + 1) / 2, npm = (long)np * (np - 1) / 2;
+  const long pairs = (long)rows * c1;
+  const long total = pairs * (ldp + ldm);
+  const long ld = (long)c1 * np;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
+    const bool plus = t < pairs * ldp;
+    const long u = plus ? t : t - pairs * ldp;
+    const long ldq = plus ? ldp : ldm;
+    const long pr = u / ldq, q = u % ldq;
+    if (q >= (plus ? npp : npm)) {
+      if (plus) wp[u] = (T)0; else wm[u] = (T)0;
+      continue;
+    }
+    const int cr = (int)(pr / c1), d = (int)(pr % c1);
+    int e;
+    if (plus) {
+      e = (int)((sqrt(8.0 * q + 1.0) - 1.0) / 2.0);
+      while ((long)e * (e + 1) / 2 > q) --e;
+      while ((long)(e + 1) * (e + 2) / 2 <= q) ++e;
+    } else {
+      e = (int)((sqrt(8.0 * q + 1.0) + 1.0) / 2.0);
+      while ((long)e * (e - 1) / 2 > q) --e;
+      while ((long)(e + 1) * e / 2 <= q) ++e;
+    }
+    const int f = plus ? (int)(q - (long)e * (e + 1) / 2) : (int)(q - (long)e * (e - 1) / 2);
+    const T a = wsrc[((long)cr * np + e) * ld + (long)d * np + f];
+    const T b = wsrc[((long)cr * np + f) * ld + (long)d * np + e];
+    if (plus) wp[u] = a + b;
+    else wm[u] = a - b;
+  }
+}
+
+// R2 from S+[kl+][(c - c0) c1 + d] and S-[kl-][...] for d <= c (pair symmetry fills d > c)
+__global__ void ladder_scatter_pm(const double* __restrict__ sp, const double* __restrict__ sm, int nh, int np,
+                                  int c0, int c1, double* __restrict__ r2) {
+  const long nhp = (long)nh * (nh + 1) / 2;
+  const long cols = (long)(c1 - c0) * c1;
+  const long total = nhp * cols;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
+    const long r = t / cols, j = t % cols;
+    const int c = c0 + (int)(j / c1), d = (int)(j % c1);
+    if (d > c) continue;
+    int l = (int)((sqrt(8.0 * r + 1.0) - 1.0) / 2.0);
+    while ((long)l * (l + 1) / 2 > r) --l;
+    while ((long)(l + 1) * (l + 2) / 2 <= r) ++l;
+    const int k = (int)(r - (long)l * (l + 1) / 2);
+    const double vp = sp[t];
+    // the minus part vanishes identically for k == l and for c == d
+    const double vm = (k < l && d < c) ? sm[((long)l * (l - 1) / 2 + k) * cols + j] : 0.0;
+    const double a = vp + vm, b = vp - vm;   // (k,l,c,d) and (l,k,c,d)
+    r2[(((long)k * nh + l) * np + c) * np + d] += a;
+    if (k < l) r2[(((long)l * nh + k) * np + c) * np + d] += b;
+    if (d < c) {
+      r2[(((long)l * nh + k) * np + d) * np + c] += a;
+      if (k < l) r2[(((long)k * nh + l) * np + d) * np + c] += b;
+    }
+  }
+}
+
 }  // namespace
 
 // ---- launchers ------------------------------------------------------------------------------
@@ -409,6 +523,46 @@ hipError_t prepare_cumulants(const double* g1, const double* g2, const double* g
 hipError_t reference_energy(const double* f, int n, const double* I4, int nc, int na, const double* g1,
                             const double* g2, double* out, hipStream_t st) {
   hipLaunchKernelGGL(e0_kernel, dim3(1), dim3(kThreads), 0, st, f, n, I4, nc, na, g1, g2, out);
+  return hipGetLastError();
+}
+
+hipError_t pack_tau(const double* tau, int nh, int np, double* tp, double* tm, long ldp, long ldm, hipStream_t st) {
+  const long n = (long)nh * (nh + 1) / 2 * ldp + (long)nh * (nh - 1) / 2 * ldm;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL((pack_tau_kernel<double>), dim3(blocks_for(n)), dim3(kThreads), 0, st, tau, nh, np, tp, tm, ldp,
+                     ldm);
+  return hipGetLastError();
+}
+
+hipError_t pack_tau_f32(const double* tau, int nh, int np, float* tp, float* tm, long ldp, long ldm, hipStream_t st) {
+  const long n = (long)nh * (nh + 1) / 2 * ldp + (long)nh * (nh - 1) / 2 * ldm;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL((pack_tau_kernel<float>), dim3(blocks_for(n)), dim3(kThreads), 0, st, tau, nh, np, tp, tm, ldp,
+                     ldm);
+  return hipGetLastError();
+}
+
+hipError_t pack_w(const double* w, int np, int rows, int c1, double* wp, double* wm, long ldp, long ldm,
+                  hipStream_t st) {
+  const long n = (long)rows * c1 * (ldp + ldm);
+  hipLaunchKernelGGL((pack_w_kernel<double>), dim3(blocks_for(n)), dim3(kThreads), 0, st, w, np, rows, c1, wp, wm,
+                     ldp, ldm);
+  return hipGetLastError();
+}
+
+hipError_t pack_w_f32(const float* w, int np, int rows, int c1, float* wp, float* wm, long ldp, long ldm,
+                      hipStream_t st) {
+  const long n = (long)rows * c1 * (ldp + ldm);
+  hipLaunchKernelGGL((pack_w_kernel<float>), dim3(blocks_for(n)), dim3(kThreads), 0, st, w, np, rows, c1, wp, wm,
+                     ldp, ldm);
+  return hipGetLastError();
+}
+
+hipError_t ladder_scatter_pm_add(const double* sp, const double* sm, int nh, int np, int c0, int c1, double* r2,
+                                 hipStream_t st) {
+  const long n = (long)nh * (nh + 1) / 2 * ((long)(c1 - c0) * c1);
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(ladder_scatter_pm, dim3(blocks_for(n)), dim3(kThreads), 0, st, sp, sm, nh, np, c0, c1, r2);
   return hipGetLastError();
 }
 

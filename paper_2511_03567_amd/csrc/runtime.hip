@@ -201,7 +201,7 @@ struct ric_ctx {
 
   // owned device tensors
   DevBuf f, eps, B, BT, BT32, g1, g2, g3, ga, ea, l2, k2, l3, k3, I4, I3, IJ, IK, tau, Edev, red, e0;
-  DevBuf scrA, scrB, scrC, scrK, wbuf, wbuf2, lad32, dfa, dfb;
+  DevBuf scrA, scrB, scrC, scrC2, scrK, wbuf, wbuf2, lad32, dfa, dfb;
   Pool pool;
   int precision = RIC_FP64;
   double ladder_ms = 0.0, total_ms = 0.0;
@@ -210,7 +210,7 @@ struct ric_ctx {
 
   ~ric_ctx() {
     for (DevBuf* b : {&f, &eps, &B, &BT, &BT32, &g1, &g2, &g3, &ga, &ea, &l2, &k2, &l3, &k3, &I4, &I3, &IJ, &IK,
-                      &tau, &Edev, &red, &e0, &scrA, &scrB, &scrC, &scrK, &wbuf, &wbuf2, &lad32, &dfa, &dfb})
+                      &tau, &Edev, &red, &e0, &scrA, &scrB, &scrC, &scrC2, &scrK, &wbuf, &wbuf2, &lad32, &dfa, &dfb})
       b->release();
     pool.release();
     for (auto& e : ev)
@@ -614,39 +614,42 @@ struct ric_ctx {
   }
 
   // -- ladder: R2[k,l,c,d] += sum_{e,f} (ce|df) tau[k,l,e,f] ------------------------------------
+  // With tau pair-symmetric, only c >= d is built: W[c,d,e,f] = (ce|df) from B in chunks of c,
+  // packed to W+/- over e >= f (e > f) and contracted with tau+/- over k <= l (k < l):
+  // R2[k,l,c,d] = S+[kl,cd] + S-[kl,cd], R2[l,k,c,d] = S+ - S-, R2[l,k,d,c] = R2[k,l,c,d].
   void ladder(const double* taup, double* r2) {
-    const int nc = sz.nc, np_ = sz.na + sz.nv, nh = sz.nc + sz.na, nx = sz.naux;
+    const int np_ = sz.na + sz.nv, nh = sz.nc + sz.na, nx = sz.naux;
     if (np_ == 0 || nh == 0) return;
     const long pp = (long)np_ * np_;
+    const long nhp = (long)nh * (nh + 1) / 2, nhm = (long)nh * (nh - 1) / 2;
+    const long npp = (long)np_ * (np_ + 1) / 2, npm = (long)np_ * (np_ - 1) / 2;
+    const long ldp = (npp + 3) / 4 * 4, ldm = std::max<long>(4, (npm + 3) / 4 * 4);
     const bool mixed = precision == RIC_FP32MIX;
     if (BT.n < (size_t)pp * nx) throw Err(RIC_E_STATE, "DF factors not loaded");
-    // tau in fp32 for the mixed path
-    const float* tau32 = nullptr;
-    if (mixed) {
-      lad32.ensure(((size_t)nh * nh * pp + 1) / 2);
-      Iter it;
-      it.nd = 1;
-      it.total = (long)nh * nh * pp;
-      it.ext[0] = it.total;
-      it.so[0] = 1;
-      it.si[0] = 1;
-      HIPCHK(ric::strided_copy_f32(it, 1.0, taup, reinterpret_cast<float*>(lad32.p), stream));
-      tau32 = reinterpret_cast<const float*>(lad32.p);
-    }
-    // chunk of c rows.  W'[(c,e)][(d,f)] = sum_X BT[c][e][X] BT[d][f][X] for d < c1 is one
-    // large GEMM (M = rows*nP, N = c1*nP, K = naux); it is then permuted to
-    // W[(c,d)][(e,f)] so that (e,f) is the contiguous contraction index.
-    const double budget = 1.4e9;  // elements of W per chunk (two buffers)
+    // packed tau (fp64, or fp32 for the mixed path)
+    const size_t tel = (size_t)nhp * ldp + (size_t)nhm * ldm;
+    lad32.ensure(mixed ? (tel + 1) / 2 : tel);
+    double* tpd = lad32.p;
+    double* tmd = lad32.p + (size_t)nhp * ldp;
+    float* tpf = reinterpret_cast<float*>(lad32.p);
+    float* tmf = tpf + (size_t)nhp * ldp;
+    if (mixed) HIPCHK(ric::pack_tau_f32(taup, nh, np_, tpf, tmf, ldp, ldm, stream));
+    else HIPCHK(ric::pack_tau(taup, nh, np_, tpd, tmd, ldp, ldm, stream));
+    // chunk of c rows: W'[(c,e)][(d,f)] (one GEMM), then W+/- per (c,d) pair
+    const double budget = 1.4e9;  // elements of W' per chunk
     long chunk = std::max<long>(1, (long)(budget / ((double)np_ * pp)));
     chunk = std::min<long>(chunk, np_);
-    const size_t welems = (size_t)chunk * np_ * pp;
-    wbuf.ensure(mixed ? (welems + 1) / 2 : welems);
-    wbuf2.ensure(mixed ? (welems + 1) / 2 : welems);
-    scrC.ensure((size_t)nh * nh * chunk * np_);
+    const size_t wel = (size_t)chunk * np_ * pp;
+    const size_t pel = (size_t)chunk * np_ * (ldp + ldm);
+    wbuf.ensure(mixed ? (pel + 1) / 2 : pel);
+    wbuf2.ensure(mixed ? (wel + 1) / 2 : wel);
+    scrC.ensure((size_t)nhp * chunk * np_);
+    scrC2.ensure((size_t)std::max<long>(1, nhm) * chunk * np_);
     scrK.ensure(64L * 1024 * 1024);
     for (int c0 = 0; c0 < np_; c0 += (int)chunk) {
       const int c1 = std::min<int>(np_, c0 + (int)chunk);
       const int rows = c1 - c0;
+      const long pairs = (long)rows * c1;
       GemmArgs g;
       g.M = rows * np_;
       g.N = c1 * np_;
@@ -654,39 +657,41 @@ struct ric_ctx {
       g.lda = nx;
       g.ldb = nx;
       g.ldc = (long)c1 * np_;
-      Iter it;  // W[c][d][e][f] <- W'[c][e][d][f]
-      it.nd = 4;
-      it.ext[0] = rows; it.ext[1] = c1; it.ext[2] = np_; it.ext[3] = np_;
-      it.so[0] = (long)c1 * pp; it.so[1] = pp; it.so[2] = np_; it.so[3] = 1;
-      it.si[0] = (long)np_ * c1 * np_; it.si[1] = np_; it.si[2] = (long)c1 * np_; it.si[3] = 1;
-      it.total = (long)rows * c1 * pp;
+      GemmArgs hp, hm;
+      hp.M = (int)nhp;
+      hp.N = (int)pairs;
+      hp.K = (int)ldp;
+      hp.lda = ldp;
+      hp.ldb = ldp;
+      hp.C = scrC.p;
+      hp.ldc = pairs;
+      hm = hp;
+      hm.M = (int)nhm;
+      hm.K = (int)ldm;
+      hm.lda = ldm;
+      hm.ldb = ldm;
+      hm.C = scrC2.p;
       if (!mixed) {
         g.C = wbuf2.p;
         HIPCHK(ric::gemm_nt_f64(g, BT.p + (long)c0 * np_ * nx, BT.p, stream, scrK.p, scrK.n));
-        HIPCHK(ric::strided_copy(it, 1.0, wbuf2.p, 0.0, wbuf.p, stream));
+        double* wp = wbuf.p;
+        double* wm = wbuf.p + (size_t)pairs * ldp;
+        HIPCHK(ric::pack_w(wbuf2.p, np_, rows, c1, wp, wm, ldp, ldm, stream));
+        HIPCHK(ric::gemm_nt_f64(hp, tpd, wp, stream, scrK.p, scrK.n));
+        if (nhm > 0) HIPCHK(ric::gemm_nt_f64(hm, tmd, wm, stream, scrK.p, scrK.n));
       } else {
+        float* w2 = reinterpret_cast<float*>(wbuf2.p);
         HIPCHK(ric::gemm_nt_f32_out32(g, reinterpret_cast<const float*>(BT32.p) + (long)c0 * np_ * nx,
-                                      reinterpret_cast<const float*>(BT32.p), reinterpret_cast<float*>(wbuf2.p),
-                                      stream));
-        HIPCHK(ric::strided_copy_f32f32(it, reinterpret_cast<const float*>(wbuf2.p),
-                                        reinterpret_cast<float*>(wbuf.p), stream));
+                                      reinterpret_cast<const float*>(BT32.p), w2, stream));
+        float* wp = reinterpret_cast<float*>(wbuf.p);
+        float* wm = wp + (size_t)pairs * ldp;
+        HIPCHK(ric::pack_w_f32(w2, np_, rows, c1, wp, wm, ldp, ldm, stream));
+        HIPCHK(ric::gemm_nt_f32(hp, tpf, wp, stream, scrK.p, scrK.n));
+        if (nhm > 0) HIPCHK(ric::gemm_nt_f32(hm, tmf, wm, stream, scrK.p, scrK.n));
       }
-      // contraction: C[kl][(c - c0) * c1 + d] = sum_ef tau[kl][ef] W[(c,d)][ef]
-      GemmArgs h;
-      h.M = nh * nh;
-      h.N = rows * c1;
-      h.K = (int)pp;
-      h.lda = pp;
-      h.ldb = pp;
-      h.C = scrC.p;
-      h.ldc = h.N;
-      if (!mixed)
-        HIPCHK(ric::gemm_nt_f64(h, taup, wbuf.p, stream, scrK.p, scrK.n));
-      else
-        HIPCHK(ric::gemm_nt_f32(h, tau32, reinterpret_cast<const float*>(wbuf.p), stream, scrK.p, scrK.n));
-      HIPCHK(ric::ladder_scatter_add(scrC.p, nh, np_, c0, c1, c1, r2, stream));
+      if (nhm == 0) HIPCHK(ric::fill(scrC2.p, 1, 0.0, stream));
+      HIPCHK(ric::ladder_scatter_pm_add(scrC.p, scrC2.p, nh, np_, c0, c1, r2, stream));
     }
-    (void)nc;
   }
 
   // -- plan execution -----------------------------------------------------------------------
