@@ -22,6 +22,11 @@ PEAK_FP64 = 78.6      # TFLOP/s, dense MFMA
 PEAK_FP32 = 157.3
 METRIC = "s/residual-iteration & TFLOP/s, 809-orb CAS(12,12); FP32-mixed vs FP64 at 1e-6 Eh"
 
+# HBM bytes of one ladder call at the 809-orbital shape, from the FETCH_SIZE / WRITE_SIZE passes in
+# profiles/ladder_b12_cas1212_hbm_counters.md (scaled by the copy-kernel calibration).  Valid only
+# for the kernel sources they were taken on; any change to them reports null.
+LADDER_TRAFFIC = {"bytes": 8.931e13, "sources_sha256": "8f05ada41255ec66", "workload": "b12_cas1212"}
+
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
@@ -77,6 +82,17 @@ def plan_flops(nc, na, nv, naux, plan_path):
                 ladder += lad
                 total += lad
     return total, ladder
+
+
+def ladder_traffic(config):
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2511_03567_amd", "csrc")
+    h = hashlib.sha256()
+    for f in ("gemm.hip", "kernels.hip"):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    ok = h.hexdigest()[:16] == LADDER_TRAFFIC["sources_sha256"] and config == LADDER_TRAFFIC["workload"]
+    return LADDER_TRAFFIC["bytes"] if ok else None
 
 
 def cpu_baseline(flops_full, plan_path):
@@ -152,10 +168,28 @@ def main():
     torch.cuda.synchronize()
     log("inputs loaded on the device")
     s1, s2 = ctx.amplitude_shapes()
-    T1 = torch.zeros(s1, dtype=torch.float64, device=dev)
-    T2 = torch.zeros(s2, dtype=torch.float64, device=dev)
+    # seeded amplitudes of first-order size (std 1e-2), pair-symmetric, all-active block zero
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(cfg.seed)
+    T1 = torch.randn(s1, dtype=torch.float64, device=dev, generator=gen) * 1e-2
+    T2 = torch.randn(s2, dtype=torch.float64, device=dev, generator=gen) * 1e-2
+    T2.add_(T2.permute(1, 0, 3, 2).contiguous()).mul_(0.5)
+    T1[cfg.nc:, :cfg.na] = 0.0
+    T2[cfg.nc:, cfg.nc:, :cfg.na, :cfg.na] = 0.0
+    T1s, T2s = T1.clone(), T2.clone()
     R1 = torch.empty_like(T1)
     R2 = torch.empty_like(T2)
+    torch.cuda.synchronize()
+    log("amplitudes initialized")
+
+    # a plain copy of known size (1 GiB read, 1 GiB written), outside the timed
+    # region: hardware byte counters of the other kernels are scaled by what they
+    # read for it
+    ca = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    cb = torch.mul(ca, 1.0)
+    torch.cuda.synchronize()
+    del ca, cb
+    log("calibration copy done (1 GiB read, 1 GiB written)")
 
     def step(prec):
         ctx.residual(T1, T2, R1, R2, prec)
@@ -197,20 +231,35 @@ def main():
                    "global_batch": 1, "parallelism": "single GPU"},
         "tflops": flops / dt / 1e12,
         "algorithmic_flops": flops,
-        "roofline": {"bound": "mfma", "kernel": "particle-particle ladder (gemm_nt_kernel f64)",
+        "roofline": {"bound": "mfma",
+                     "kernel": "particle-particle ladder (gemm_nt_kernel<double,...,Site=1> W build and +/- products, "
+                               "pack_tau/pack_w/ladder_scatter_pm, splitk_reduce<1>)",
                      "achieved": lflops / ladder_s / 1e12 if ladder_s > 0 else None,
                      "peak": PEAK_FP64, "unit": "TFLOP/s",
                      "frac": (lflops / ladder_s / 1e12) / PEAK_FP64 if ladder_s > 0 else None,
-                     "traffic": None, "ladder_s": ladder_s, "ladder_algorithmic_flops": lflops},
+                     "traffic": ladder_traffic(args.config), "ladder_s": ladder_s,
+                     "ladder_algorithmic_flops": lflops},
+        "nonladder_tflops": (flops - lflops) / (dt - ladder_s) / 1e12 if dt > ladder_s else None,
     }
     if not args.no_mixed:
+        # FP32-mixed residual at the starting amplitudes, against the FP64 one there
+        if args.steps + args.warmup != 1:
+            ctx.residual(T1s, T2s, R1, R2, ric.RIC_FP64)
+            torch.cuda.synchronize()
+            log("fp64 reference residual at the starting amplitudes done")
+        Rm1 = torch.empty_like(R1)
+        Rm2 = torch.empty_like(R2)
         t0 = time.perf_counter()
-        ctx.residual(T1, T2, R1, R2, ric.RIC_FP32MIX)
+        ctx.residual(T1s, T2s, Rm1, Rm2, ric.RIC_FP32MIX)
         torch.cuda.synchronize()
         mix = time.perf_counter() - t0
         lm, tm = ctx.timings()
         log(f"fp32-mixed residual done: {mix:.1f} s, ladder {lm / 1e3:.1f} s")
+        scale = max(R1.abs().max().item(), R2.abs().max().item())
+        diff = max((Rm1 - R1).abs().max().item(), (Rm2 - R2).abs().max().item())
+        del Rm1, Rm2
         out["fp32mix_residual_s"] = mix
+        out["fp32mix_residual_max_rel_diff"] = diff / scale
         out["fp32mix_ladder_tflops"] = lflops / (lm / 1e3) / 1e12 if lm > 0 else None
         out["fp32mix_ladder_frac_of_fp32_peak"] = (lflops / (lm / 1e3) / 1e12) / PEAK_FP32 if lm > 0 else None
     if not args.no_cpu_baseline:

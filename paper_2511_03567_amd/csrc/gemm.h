@@ -13,6 +13,7 @@ struct GemmArgs {
   int batch = 1;          // number of C matrices
   int zdiv = 1;           // batch z uses A[z / zdiv], B[z % zdiv], C[z]
   long strideA = 0, strideB = 0, strideC = 0;
+  int site = 0;           // 1: particle-particle ladder (a separate kernel symbol for profiles)
 };
 
 // scratch: fp64 workspace for split-K partial tiles (may be null when scratch_elems == 0)

@@ -157,7 +157,9 @@ __device__ inline void stash(T* As, T* Bs, int tid, const Slab<T, Gm>& s) {
 
 // Tile kernel.  Acc is the MFMA accumulator type; for fp32 operands the
 // per-slab fp32 result is added into fp64 registers (acc64).
-template <typename T, typename Acc, typename TC, typename Gm, bool VEC>
+// Site only separates the symbols of call sites that profiles attribute
+// (0: general contractions, 1: particle-particle ladder).
+template <typename T, typename Acc, typename TC, typename Gm, bool VEC, int Site>
 __global__ void __launch_bounds__(Gm::NT, Gm::MINB)
 gemm_nt_kernel(int M, int N, int K, double alpha, const T* __restrict__ A, long lda,
                const T* __restrict__ B, long ldb, double beta, TC* __restrict__ C, long ldc,
@@ -278,6 +280,7 @@ gemm_nt_kernel(int M, int N, int K, double alpha, const T* __restrict__ A, long 
 int g_variant = -1;  // -1: default geometry; >= 0 forces one (benchmarking)
 
 // Sum of split-K partial tiles in a fixed order (deterministic), then alpha/beta.
+template <int Site>
 __global__ void splitk_reduce(int M, int N, int ksplit, int batches, double alpha, double beta,
                               const double* __restrict__ partial, long strideP, double* __restrict__ C,
                               long ldc, long strideC) {
@@ -294,7 +297,7 @@ __global__ void splitk_reduce(int M, int N, int ksplit, int batches, double alph
   }
 }
 
-template <typename T, typename Acc, typename TC, typename Gm>
+template <typename T, typename Acc, typename TC, typename Gm, int Site = 0>
 hipError_t launch_geo(const GemmArgs& g, const T* A, const T* B, TC* C, hipStream_t st, double* scratch,
                       size_t scratch_elems) {
   constexpr int BM = Gm::BM, BN = Gm::BN;
@@ -315,17 +318,17 @@ hipError_t launch_geo(const GemmArgs& g, const T* A, const T* B, TC* C, hipStrea
   dim3 grid(tiles, 1, g.batch * ksplit);
   const long strideP = (long)g.M * g.N;
   if (vec)
-    hipLaunchKernelGGL((gemm_nt_kernel<T, Acc, TC, Gm, true>), grid, dim3(Gm::NT), 0, st, g.M, g.N, g.K, g.alpha, A,
+    hipLaunchKernelGGL((gemm_nt_kernel<T, Acc, TC, Gm, true, Site>), grid, dim3(Gm::NT), 0, st, g.M, g.N, g.K, g.alpha, A,
                        g.lda, B, g.ldb, g.beta, C, g.ldc, g.strideA, g.strideB, g.strideC, g.zdiv, ksplit, strideP,
                        scratch);
   else
-    hipLaunchKernelGGL((gemm_nt_kernel<T, Acc, TC, Gm, false>), grid, dim3(Gm::NT), 0, st, g.M, g.N, g.K, g.alpha, A,
+    hipLaunchKernelGGL((gemm_nt_kernel<T, Acc, TC, Gm, false, Site>), grid, dim3(Gm::NT), 0, st, g.M, g.N, g.K, g.alpha, A,
                        g.lda, B, g.ldb, g.beta, C, g.ldc, g.strideA, g.strideB, g.strideC, g.zdiv, ksplit, strideP,
                        scratch);
   if (ksplit > 1) {
     const long total = (long)g.batch * g.M * g.N;
     const int nb = (int)std::min<long>((total + 255) / 256, 65536);
-    hipLaunchKernelGGL(splitk_reduce, dim3(nb), dim3(256), 0, st, g.M, g.N, ksplit, g.batch, g.alpha,
+    hipLaunchKernelGGL(splitk_reduce<Site>, dim3(nb), dim3(256), 0, st, g.M, g.N, ksplit, g.batch, g.alpha,
                        g.beta, scratch, strideP, reinterpret_cast<double*>(C), g.ldc, g.strideC);
   }
   return hipGetLastError();
@@ -343,6 +346,11 @@ hipError_t launch(const GemmArgs& g, const T* A, const T* B, TC* C, hipStream_t 
                   size_t scratch_elems) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
   if (g.K <= 0 && g.beta == 1.0) return hipSuccess;
+  if (g.site == 1) {
+    // the ladder's products always take the default tile shape of their type
+    if constexpr (sizeof(T) == 8) return launch_geo<T, Acc, TC, G128x16b2, 1>(g, A, B, C, st, scratch, scratch_elems);
+    else return launch_geo<T, Acc, TC, G128x32, 1>(g, A, B, C, st, scratch, scratch_elems);
+  }
   int v = g_variant;
   // measured on gfx950: fp64 best with 128x128x16 tiles at two workgroups per CU,
   // fp32 with 128x128x32 tiles

@@ -201,7 +201,7 @@ struct ric_ctx {
 
   // owned device tensors
   DevBuf f, eps, B, BT, BT32, g1, g2, g3, ga, ea, l2, k2, l3, k3, I4, I3, IJ, IK, tau, Edev, red, e0;
-  DevBuf scrA, scrB, scrC, scrC2, scrK, wbuf, wbuf2, lad32, dfa, dfb;
+  DevBuf scrA, scrB, scrC, scrC2, scrK, wbuf, wbuf2, lad32, dfa, dfb, dfz;
   Pool pool;
   int precision = RIC_FP64;
   double ladder_ms = 0.0, total_ms = 0.0;
@@ -210,7 +210,7 @@ struct ric_ctx {
 
   ~ric_ctx() {
     for (DevBuf* b : {&f, &eps, &B, &BT, &BT32, &g1, &g2, &g3, &ga, &ea, &l2, &k2, &l3, &k3, &I4, &I3, &IJ, &IK,
-                      &tau, &Edev, &red, &e0, &scrA, &scrB, &scrC, &scrC2, &scrK, &wbuf, &wbuf2, &lad32, &dfa, &dfb})
+                      &tau, &Edev, &red, &e0, &scrA, &scrB, &scrC, &scrC2, &scrK, &wbuf, &wbuf2, &lad32, &dfa, &dfb, &dfz})
       b->release();
     pool.release();
     for (auto& e : ev)
@@ -555,9 +555,92 @@ struct ric_ctx {
   }
 
   // -- (pr|qs) = sum_X L1[X,p,r] L2[X,q,s] built block by block and contracted with y ---------
+  // Product of the extents of the distinct labels of `vs` (label X of the DF factors excluded
+  // when skip >= 0).
+  static double label_volume(std::initializer_list<const View*> vs, int skip) {
+    std::map<int, long> ex;
+    for (const View* v : vs)
+      for (int i = 0; i < v->nd; ++i) ex[v->lab[i]] = v->ext[i];
+    double p = 1.0;
+    for (auto& kv : ex)
+      if (kv.first != skip) p *= (double)kv.second;
+    return p;
+  }
+
+  // out += alpha * sum (pr|qs) y without forming (pr|qs): Z = Lb . y over the labels of Lb that
+  // y holds and neither out nor La does, then out += alpha * La . Z (sum over X and the labels
+  // La shares with Z).  Returns false when a label would have to be carried through both
+  // products (a batch label).  With dry = true only the flops and the size of Z are reported.
+  bool dfc_through_factors(const View& out, double alpha, const View& La, const View& Lb, const View& y, bool dry,
+                           double& flops, double& zsize) {
+    const int xl = Lb.lab[0];
+    std::vector<int> zl{xl};
+    std::vector<long> ze{Lb.ext[0]};
+    for (int i = 1; i < Lb.nd; ++i) {
+      const int l = Lb.lab[i];
+      const bool summed = y.find(l) >= 0 && out.find(l) < 0 && La.find(l) < 0;
+      if (summed) continue;
+      if (y.find(l) >= 0) return false;
+      zl.push_back(l);
+      ze.push_back(Lb.ext[i]);
+    }
+    for (int i = 0; i < y.nd; ++i) {
+      if (Lb.find(y.lab[i]) >= 0) continue;
+      zl.push_back(y.lab[i]);
+      ze.push_back(y.ext[i]);
+    }
+    if ((int)zl.size() > kMaxDims) return false;
+    for (size_t i = 1; i < zl.size(); ++i)
+      if (La.find(zl[i]) >= 0 && out.find(zl[i]) >= 0) return false;
+    for (int i = 0; i < out.nd; ++i)
+      if (La.find(out.lab[i]) < 0 && std::find(zl.begin(), zl.end(), out.lab[i]) == zl.end()) return false;
+    View z;
+    z.nd = (int)zl.size();
+    long st = 1;
+    for (int i = z.nd - 1; i >= 0; --i) {
+      z.lab[i] = zl[i];
+      z.ext[i] = ze[i];
+      z.str[i] = st;
+      st *= ze[i];
+    }
+    const double nx = (double)Lb.ext[0];
+    flops = 2.0 * nx * label_volume({&Lb, &y}, xl) + 2.0 * nx * label_volume({&La, &z}, xl);
+    zsize = (double)st;
+    if (dry) return true;
+    dfz.ensure((size_t)std::max<long>(st, 1));
+    z.p = dfz.p;
+    contract(z, 1.0, Lb, y, true, true);
+    contract(out, alpha, La, z, false, true);
+    return true;
+  }
+
   void dfc(const View& out, double alpha, const View& L1, const View& L2, const View& y) {
     const long np_ = L1.ext[1], nr = L1.ext[2], nq = L2.ext[1], ns = L2.ext[2], nx = L1.ext[0];
     if (np_ == 0 || nr == 0 || nq == 0 || ns == 0) return;
+    {
+      // the cheaper of building the integral block and going through the factors
+      View e;
+      e.nd = 4;
+      const int lb4[4] = {L1.lab[1], L1.lab[2], L2.lab[1], L2.lab[2]};
+      const long ex4[4] = {np_, nr, nq, ns};
+      for (int i = 0; i < 4; ++i) {
+        e.lab[i] = lb4[i];
+        e.ext[i] = ex4[i];
+      }
+      const double build = 2.0 * (double)nx * np_ * nr * nq * ns + 2.0 * label_volume({&e, &y, &out}, -1);
+      double f1 = 0, z1 = 0, f2 = 0, z2 = 0;
+      const double zmax = 2.0e9;
+      bool ok1 = dfc_through_factors(out, alpha, L1, L2, y, true, f1, z1) && z1 <= zmax;
+      bool ok2 = dfc_through_factors(out, alpha, L2, L1, y, true, f2, z2) && z2 <= zmax;
+      if (ok1 && (!ok2 || f1 <= f2) && f1 < build) {
+        dfc_through_factors(out, alpha, L1, L2, y, false, f1, z1);
+        return;
+      }
+      if (ok2 && f2 < build) {
+        dfc_through_factors(out, alpha, L2, L1, y, false, f2, z2);
+        return;
+      }
+    }
     // L2 as [(q,s)][X]
     DevBuf& l2buf = dfb;
     l2buf.ensure((size_t)nq * ns * nx);
@@ -657,6 +740,7 @@ struct ric_ctx {
       g.lda = nx;
       g.ldb = nx;
       g.ldc = (long)c1 * np_;
+      g.site = 1;
       GemmArgs hp, hm;
       hp.M = (int)nhp;
       hp.N = (int)pairs;
@@ -665,6 +749,7 @@ struct ric_ctx {
       hp.ldb = ldp;
       hp.C = scrC.p;
       hp.ldc = pairs;
+      hp.site = 1;
       hm = hp;
       hm.M = (int)nhm;
       hm.K = (int)ldm;

@@ -25,6 +25,7 @@ def main():
         if args.terms_cache:
             with open(args.terms_cache, "wb") as fh:
                 pickle.dump((e, r1, s2), fh)
+    s2 = algebra.merge_pair_images(s2)   # idempotent; also applied to cached term lists
     t1 = time.time()
     plan, res_flops = comp.compile_plan(e, r1, s2)
     text = "\n".join(plan.lines) + "\n"

@@ -468,6 +468,26 @@ def merge_sf(terms):
     return out
 
 
+def merge_pair_images(s2_terms):
+    """Merge S2 terms modulo the pair swap (k,l,c,d) -> (l,k,d,c).
+
+    Only S2 + S2^T(pairs) enters R2, so a term and the pair-swapped image of
+    another are interchangeable: each term is replaced by whichever of itself and
+    its image has the smaller canonical key, and equal keys are summed.
+    """
+    acc = {}
+    rep = {}
+    for t in s2_terms:
+        k, l, c, d = t.ext
+        img = SFTerm(t.coef, t.factors, (l, k, d, c), t.rng)
+        key, kimg = canonical_key(t), canonical_key(img)
+        if kimg < key:
+            key, t = kimg, img
+        acc[key] = acc.get(key, 0) + t.coef
+        rep.setdefault(key, t)
+    return [SFTerm(c, rep[k].factors, rep[k].ext, rep[k].rng) for k, c in acc.items() if c != 0]
+
+
 # ---- the residual and energy equations ----------------------------------------------------
 
 EXT_T2_RANGES = (C, C, V, V)
@@ -531,4 +551,4 @@ def derive():
             s2_terms += spin_integrate(t2, (l1, l2, u1, u2), (0, 1, 0, 1))
             neg = SOTerm(-t.coef, t.tensors, t.upper, t.lower, rr, t.has_l2)
             s2_terms += spin_integrate(neg, (l1, l2, u2, u1), (0, 1, 0, 1))
-    return merge_sf(e_terms), merge_sf(r1_terms), merge_sf(s2_terms)
+    return merge_sf(e_terms), merge_sf(r1_terms), merge_pair_images(merge_sf(s2_terms))

@@ -17,8 +17,10 @@ PLAN_PATH = os.path.join(_HERE, "plan.txt")
 RIC_FP64 = 0
 RIC_FP32MIX = 1
 
+RIC_E_NOCONV = -7   # raised by solve() only: the iteration did not reach the tolerance
+
 _ERRORS = {-1: "RIC_E_ARG", -2: "RIC_E_STATE", -3: "RIC_E_OOM", -4: "RIC_E_HIP",
-           -5: "RIC_E_NONFINITE", -6: "RIC_E_PLAN"}
+           -5: "RIC_E_NONFINITE", -6: "RIC_E_PLAN", RIC_E_NOCONV: "RIC_E_NOCONV"}
 
 _lib = None
 
@@ -201,4 +203,4 @@ def solve(ctx: Context, s, tol=1e-8, max_iter=200, precision=RIC_FP64, polish_to
             e, e0 = ctx.energy(T1, T2)
             return e, e0, T1, T2, it
         prev = step
-    raise RicError(-5, "regularized iteration did not converge")
+    raise RicError(RIC_E_NOCONV, f"regularized iteration did not converge in {max_iter} iterations")

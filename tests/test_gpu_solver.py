@@ -1,0 +1,94 @@
+"""GPU solver: the regularized Jacobi iteration (eq. ric-update) in FP64 and FP32-mixed.
+
+FP64 against the oracle's converged energy (tests/golden/oracle_solve.json, written by
+make_solve_golden.py from the oracle alone): within 1e-9 E_h.  FP32-mixed iterations
+followed by FP64 polishing: within 1e-6 E_h of the oracle / of the FP64 GPU solve.
+"""
+import json
+import os
+import time
+
+import numpy as np
+import pytest
+
+import synthetic as S
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_solve.json")
+
+
+def _ctx(cfg):
+    from paper_2511_03567_amd import ric
+    inp = S.make_inputs(cfg)
+    dev = torch.device("cuda", 0)
+    ctx = ric.Context(0)
+    ctx.set_spaces(cfg.nc, cfg.na, cfg.nv, cfg.naux)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    ctx.load_fock(t(inp.f))
+    ctx.load_df(t(inp.B))
+    ctx.load_rdms(t(inp.G1), t(inp.G2), t(inp.G3))
+    return ctx
+
+
+def _golden():
+    with open(GOLDEN) as fh:
+        return json.load(fh)["cases"]
+
+
+@pytest.mark.parametrize("case", _golden(), ids=lambda c: f"{c['config']}-s{c['s']}")
+def test_solve_matches_oracle(case):
+    from paper_2511_03567_amd import ric
+    cfg = S.CONFIGS[case["config"]]
+    print(f"solve {case['config']} s={case['s']}", flush=True)
+    ctx = _ctx(cfg)
+    e64, e0, _, _, it64 = ric.solve(ctx, case["s"], tol=case["tol"])
+    emx, _, _, _, itmx = ric.solve(ctx, case["s"], tol=case["tol"], precision=ric.RIC_FP32MIX)
+    print(f"  fp64 {e64:.12f} ({it64} it)  mixed {emx:.12f} ({itmx} it)  oracle {case['e_corr']:.12f}", flush=True)
+    assert abs(e0 - case["e0"]) < 1e-9
+    assert abs(e64 - case["e_corr"]) < 1e-9
+    assert abs(it64 - case["iterations"]) <= 1
+    assert abs(emx - case["e_corr"]) < 1e-6
+
+
+@pytest.mark.parametrize("s", [0.5, 1.0])
+def test_mixed_solve_matches_fp64_cas88(s):
+    """CAS(8,8), nc=10, nv=120, naux=360: the large ring terms and the ladder run as FP32 MFMA tiles.
+
+    Where the FP64 iteration converges, the mixed iteration (then FP64 polish) reaches the
+    same energy within 1e-6 E_h.  Where it does not (plain regularized Jacobi at larger s),
+    the mixed iteration must fail the same way, following the FP64 step norms closely.
+    """
+    from paper_2511_03567_amd import ric
+    cfg = S.CONFIGS["mixed_cas88"]
+    print(f"solve mixed_cas88 s={s}", flush=True)
+    ctx = _ctx(cfg)
+    log64, logmx = [], []
+    t0 = time.perf_counter()
+    try:
+        e64, _, _, _, it64 = ric.solve(ctx, s, tol=1e-8, log=log64)
+    except ric.RicError:
+        e64 = None
+    t1 = time.perf_counter()
+    try:
+        emx, _, _, _, itmx = ric.solve(ctx, s, tol=1e-8, precision=ric.RIC_FP32MIX, log=logmx)
+    except ric.RicError:
+        emx = None
+    t2 = time.perf_counter()
+    nmix = sum(1 for r in logmx if r["precision"] == "fp32mix")
+    steps64 = [r["step"] for r in log64]
+    print(f"  fp64: {len(log64)} it, {t1 - t0:.1f} s, E {e64}; mixed: {len(logmx)} it ({nmix} mixed), "
+          f"{t2 - t1:.1f} s, E {emx}", flush=True)
+    print("  fp64 step norms every 20 iterations: " + " ".join(f"{x:.2e}" for x in steps64[::20]), flush=True)
+    assert nmix > 0
+    if e64 is not None:
+        print(f"  |dE| {abs(emx - e64):.2e}", flush=True)
+        assert abs(emx - e64) < 1e-6
+    else:
+        assert emx is None
+        n = min(nmix, 10)
+        a = np.array(steps64[:n])
+        b = np.array([r["step"] for r in logmx[:n]])
+        assert np.all(np.abs(a - b) <= 1e-5 * np.abs(a))
