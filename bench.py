@@ -32,14 +32,41 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def _dfc_flops(out, l1, l2, y, ext):
+    """Flops of out += sum (pr|qs) y as the runtime executes it: the cheaper of building the
+    integral block from the DF factors and going through the factors (Z = L.y, then L.Z)."""
+    vol = lambda labs: math.prod(ext[l] for l in set(labs))
+    nx = ext[l1[0]]
+    eri = l1[1:] + l2[1:]
+    best = 2.0 * nx * vol(eri) + 2.0 * vol(eri + y + out)
+    for la, lb in ((l1, l2), (l2, l1)):
+        zl = [lb[0]]
+        ok = True
+        for l in lb[1:]:
+            summed = l in y and l not in out and l not in la
+            if summed:
+                continue
+            if l in y:
+                ok = False
+            zl.append(l)
+        zl += [l for l in y if l not in lb]
+        ok = ok and not any(l in la and l in out for l in zl[1:])
+        ok = ok and all(l in la or l in zl for l in out)
+        if not ok or vol(zl) > 2.0e9:
+            continue
+        f = 2.0 * nx * vol([l for l in lb + y if l != lb[0]]) + 2.0 * nx * vol([l for l in la + zl if l != lb[0]])
+        best = min(best, f)
+    return best
+
+
 def plan_flops(nc, na, nv, naux, plan_path):
     """Algorithmic flops of one residual evaluation from the contraction plan.
 
-    Binary contractions: 2 * product of the extents of all their indices.  DF
-    blocks (pr|qs) built from B: 2 * naux * product of their extents plus the
-    contraction.  Ladder: W build over pairs c >= d plus the contraction with the
-    pair-packed (+/-) amplitudes, counted over the particle range P = A + V.
-    Returns (total, ladder).
+    Binary contractions: 2 * product of the extents of all their indices.  DF terms
+    (pr|qs) y: the cheaper of building the block from B plus the contraction and the
+    factored route, as the runtime chooses.  Ladder: W build over pairs c >= d plus the
+    contraction with the pair-packed (+/-) amplitudes, counted over the particle range
+    P = A + V.  Returns (total, ladder).
     """
     ext = {"C": nc, "A": na, "V": nv, "H": nc + na, "P": na + nv, "G": nc + na + nv, "X": naux}
     total = 0.0
@@ -57,24 +84,17 @@ def plan_flops(nc, na, nv, naux, plan_path):
                 continue
             if t[0] in ("CONTRACT", "CONTRACT0", "DFC"):
                 rng = {}
-                eri = []
-                for k, opd in enumerate(t[2:]):
+                labs_of = []
+                for opd in t[2:]:
                     _, r, labs = opd.split(":")
                     ls = labs.split(",") if labs else []
+                    labs_of.append(ls)
                     for x, lab in zip(r, ls):
-                        rng[lab] = x
-                    if t[0] == "DFC" and k in (1, 2):
-                        eri += list(r[1:])
-                f = 2.0
-                for lab, x in rng.items():
-                    if x != "X":
-                        f *= ext[x]
-                if eri:
-                    b = 2.0 * naux
-                    for x in eri:
-                        b *= ext[x]
-                    f += b
-                total += f
+                        rng[lab] = ext[x]
+                if t[0] == "DFC":
+                    total += _dfc_flops(labs_of[0], labs_of[1], labs_of[2], labs_of[3], rng)
+                else:
+                    total += 2.0 * math.prod(rng.values())
             elif t[0] == "LADDER":
                 nP, nH = na + nv, nc + na
                 c2 = lambda n: n * (n - 1) / 2
@@ -140,6 +160,8 @@ def main():
     ap.add_argument("--config", default="b12_cas1212")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32-mixed timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="also time one adjoint-residual evaluation (J^T x with the f and B parts)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this engine has no multi-GPU path "
@@ -262,6 +284,19 @@ def main():
         out["fp32mix_residual_max_rel_diff"] = diff / scale
         out["fp32mix_ladder_tflops"] = lflops / (lm / 1e3) / 1e12 if lm > 0 else None
         out["fp32mix_ladder_frac_of_fp32_peak"] = (lflops / (lm / 1e3) / 1e12) / PEAK_FP32 if lm > 0 else None
+    if args.adjoint:
+        # J_r^T x, (dr/df)^T x and (dr/dB)^T x at the starting amplitudes with x = R
+        n, nx = cfg.n, cfg.naux
+        dT1, dT2 = torch.empty_like(T1), torch.empty_like(T2)
+        dF = torch.empty((n, n), dtype=torch.float64, device=dev)
+        dB = torch.empty((nx, n, n), dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.adjoint_residual(T1s, T2s, R1, R2, dT1, dT2, dF, dB)
+        torch.cuda.synchronize()
+        out["adjoint_residual_s"] = time.perf_counter() - t0
+        log(f"adjoint residual done: {out['adjoint_residual_s']:.1f} s")
+        del dT1, dT2, dF, dB
     if not args.no_cpu_baseline:
         del inp
         log("timing the CPU oracle on a bounded sample")

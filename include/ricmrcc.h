@@ -109,6 +109,47 @@ int ric_energy(ric_ctx* ctx, const double* T1, const double* T2, double* e_corr,
  * For benchmarking and testing that contraction in isolation. */
 int ric_ladder(ric_ctx* ctx, const double* tau, double* R2, int precision);
 
+/* ---- adjoint (vector-Jacobian products) of the path ------------------------------------
+ * The converged amplitudes are the fixed point T = U(T) of the update of eq. ric-update,
+ * U(T) = (T Delta + r(T)) phi(Delta), phi(D) = (1 - exp(-s D^2)) / D.  The gradient of the
+ * correlation energy E(T, f, B) of Section 2.2 with respect to the Fock matrix and the DF
+ * factors follows from the Lagrange multipliers L of that fixed point:
+ *   L = dE/dT + Delta phi L + J_r^T (phi L)                                  (iteration)
+ *   dE/df = dE/df|_T + (dr/df)^T (phi L) + sum L [T phi + (T Delta + r) phi'] dDelta/df
+ *   dE/dB = dE/dB|_T + (dr/dB)^T (phi L)
+ * The calls below evaluate the pieces; the Python layer (ric.py) runs the iteration.
+ * Gradients with respect to the doubles are returned projected on pair-symmetric tensors
+ * (the space the amplitudes live in) with the excluded all-active blocks zero.  dB is the
+ * gradient with respect to every element B[P][p][q] as used (no (p,q) symmetrization). */
+
+/* J^T x for the residuals: with x = (X1, X2) (layouts of R1, R2; X2 is replaced by its
+ * pair-symmetric part, both are masked like the residuals), dT = (dr/dT)^T x and, when
+ * dF and dB are not NULL, dF = (dr/df)^T x (n x n), dB = (dr/dB)^T x (naux x n x n).
+ * The particle-particle ladder is transposed by rebuilding (ce|df) from B in chunks (for dT)
+ * and by forming sum_kl x[k,l,c,d] tau[k,l,e,f] in chunks of c (for dB); neither is stored.
+ * All outputs are overwritten.  FP64. */
+int ric_adjoint_residual(ric_ctx* ctx, const double* T1, const double* T2, const double* X1, const double* X2,
+                         double* dT1, double* dT2, double* dF, double* dB);
+
+/* Gradient of the correlation energy functional of Section 2.2 at fixed amplitudes:
+ * dT = dE/dT, dF = dE/df, dB = dE/dB.  Outputs overwritten.  FP64. */
+int ric_energy_gradient(ric_ctx* ctx, const double* T1, const double* T2, double* dT1, double* dT2, double* dF,
+                        double* dB);
+
+/* One step of the Lagrangian iteration, in place: L <- G + Delta phi(Delta) L + J over the
+ * stored amplitudes (Delta, phi as in ric_update; G = dE/dT, J = J_r^T(phi L)).
+ * step_norm2 (host, may be NULL): sum of (L_new - L)^2. */
+int ric_lambda_update(ric_ctx* ctx, double* L1, double* L2, const double* G1, const double* G2, const double* J1,
+                      const double* J2, double s, double* step_norm2);
+
+/* O = phi(Delta) L (zero on the excluded blocks): the cotangent passed to ric_adjoint_residual. */
+int ric_flow_scale(ric_ctx* ctx, const double* L1, const double* L2, double s, double* O1, double* O2);
+
+/* dF[p][p] += sum over amplitudes of L [T phi + (T Delta + R) phi'] dDelta/df_pp, the part of
+ * dE/df that enters through the denominators (R = r(T) at the converged T).  Accumulates. */
+int ric_flow_fock_gradient(ric_ctx* ctx, const double* T1, const double* T2, const double* R1, const double* R2,
+                           const double* L1, const double* L2, double s, double* dF);
+
 /* Milliseconds spent in the ladder during the last ric_residual/ric_ladder call,
  * measured with HIP events on the context stream (host output). */
 int ric_last_timings(const ric_ctx* ctx, double* ladder_ms, double* total_ms);

@@ -22,6 +22,19 @@ hipError_t strided_copy_f32f32(const Iter& it, const float* in, float* out, hipS
 hipError_t fill(double* p, long n, double v, hipStream_t st);
 hipError_t symmetrize_pairs(double* x, int nh, int np, hipStream_t st);
 hipError_t mask_active(double* r1, double* r2, int nc, int na, int nv, hipStream_t st);
+// x <- scale (x + x^T(pairs)) over [nh][nh][np][np]
+hipError_t symmetrize_pairs_scaled(double* x, int nh, int np, double scale, hipStream_t st);
+// Lagrangian iteration L <- g + Delta phi(Delta) L + j (stored amplitudes); norm2[0] = ||L_new - L||^2
+hipError_t lambda_update(double* l1, double* l2, const double* g1, const double* g2, const double* j1,
+                         const double* j2, const double* eps, int nc, int na, int nv, double s, double* partial,
+                         double* norm2, hipStream_t st);
+// o = phi(Delta) L (zero on the excluded blocks)
+hipError_t flow_scale(const double* l1, const double* l2, const double* eps, int nc, int na, int nv, double s,
+                      double* o1, double* o2, hipStream_t st);
+// df[p,p] += sum L [T phi + (T Delta + R) phi'] dDelta/df_pp
+hipError_t flow_fock_gradient(const double* t1, const double* t2, const double* r1, const double* r2,
+                              const double* l1, const double* l2, const double* eps, int nc, int na, int nv,
+                              double s, double* df, hipStream_t st);
 // out[0] += alpha * sum a[i] b[i] (deterministic two-pass); partial needs 1024 doubles
 hipError_t dot_accumulate(const double* a, const double* b, long n, double alpha, double* out, double* partial,
                           hipStream_t st);

@@ -53,7 +53,7 @@ __global__ void fill_kernel(double* __restrict__ p, long n, double v) {
 }
 
 // X[k,l,c,d] <- X[k,l,c,d] + X[l,k,d,c]; each pair handled by its lower index
-__global__ void symmetrize_kernel(double* __restrict__ x, int nh, int np) {
+__global__ void symmetrize_kernel(double* __restrict__ x, int nh, int np, double scale) {
   const long total = (long)nh * nh * np * np;
   for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
     const int d = (int)(t % np);
@@ -62,11 +62,11 @@ __global__ void symmetrize_kernel(double* __restrict__ x, int nh, int np) {
     const int k = (int)(t / ((long)np * np * nh));
     const long u = (((long)l * nh + k) * np + d) * np + c;
     if (t < u) {
-      const double s = x[t] + x[u];
+      const double s = scale * (x[t] + x[u]);
       x[t] = s;
       x[u] = s;
     } else if (t == u) {
-      x[t] = 2.0 * x[t];
+      x[t] = 2.0 * scale * x[t];
     }
   }
 }
@@ -170,6 +170,127 @@ update_kernel(double* __restrict__ t1, double* __restrict__ t2, const double* __
   }
   acc = block_sum(acc);
   if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
+// d phi / d D, with the series s (1 - 3/2 x + 5/6 x^2), x = s D^2, where the closed form cancels
+__device__ inline double dphi(double D, double s) {
+  const double x = s * D * D;
+  if (x < 1e-4) return s * (1.0 - 1.5 * x + (5.0 / 6.0) * x * x);
+  const double e = exp(-x);
+  return (2.0 * x * e + expm1(-x)) / (D * D);
+}
+
+// Lagrangian iteration L <- g + Delta phi L + j over the stored amplitudes (the excluded
+// all-active blocks stay zero); partial[b] = sum over the block's share of (L_new - L)^2
+__global__ void __launch_bounds__(kThreads)
+lambda_kernel(double* __restrict__ l1, double* __restrict__ l2, const double* __restrict__ g1,
+              const double* __restrict__ g2, const double* __restrict__ j1, const double* __restrict__ j2,
+              const double* __restrict__ eps, int nc, int na, int nv, double s, double* __restrict__ partial) {
+  const int nh = nc + na, np = na + nv;
+  const long n1 = (long)nh * np;
+  const long total = n1 + (long)nh * nh * np * np;
+  const long per = (total + gridDim.x - 1) / gridDim.x;
+  const long beg = blockIdx.x * per;
+  const long end = beg + per < total ? beg + per : total;
+  double acc = 0.0;
+  for (long t = beg + threadIdx.x; t < end; t += blockDim.x) {
+    double* l;
+    double g, j, D;
+    bool masked;
+    if (t < n1) {
+      const int k = (int)(t / np), c = (int)(t % np);
+      masked = k >= nc && c < na;
+      D = eps[k] - eps[nc + c];
+      l = l1 + t;
+      g = g1[t];
+      j = j1[t];
+    } else {
+      const long u = t - n1;
+      const int d = (int)(u % np);
+      const int c = (int)((u / np) % np);
+      const int ll = (int)((u / ((long)np * np)) % nh);
+      const int k = (int)(u / ((long)np * np * nh));
+      masked = k >= nc && ll >= nc && c < na && d < na;
+      D = eps[k] + eps[ll] - eps[nc + c] - eps[nc + d];
+      l = l2 + u;
+      g = g2[u];
+      j = j2[u];
+    }
+    const double nw = masked ? 0.0 : g + D * phi(D, s) * l[0] + j;
+    const double dv = nw - l[0];
+    acc += dv * dv;
+    l[0] = nw;
+  }
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
+// out = phi(Delta) * L, zero on the excluded blocks
+__global__ void flow_scale_kernel(const double* __restrict__ l1, const double* __restrict__ l2,
+                                  const double* __restrict__ eps, int nc, int na, int nv, double s,
+                                  double* __restrict__ o1, double* __restrict__ o2) {
+  const int nh = nc + na, np = na + nv;
+  const long n1 = (long)nh * np;
+  const long total = n1 + (long)nh * nh * np * np;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
+    if (t < n1) {
+      const int k = (int)(t / np), c = (int)(t % np);
+      const double D = eps[k] - eps[nc + c];
+      o1[t] = (k >= nc && c < na) ? 0.0 : phi(D, s) * l1[t];
+    } else {
+      const long u = t - n1;
+      const int d = (int)(u % np);
+      const int c = (int)((u / np) % np);
+      const int ll = (int)((u / ((long)np * np)) % nh);
+      const int k = (int)(u / ((long)np * np * nh));
+      const double D = eps[k] + eps[ll] - eps[nc + c] - eps[nc + d];
+      o2[u] = (k >= nc && ll >= nc && c < na && d < na) ? 0.0 : phi(D, s) * l2[u];
+    }
+  }
+}
+
+// w = L [T phi + (T Delta + R) phi'] of one amplitude (its dU/dDelta weighted by L)
+__device__ inline double flow_weight(double l, double t, double r, double D, double s) {
+  return l * (t * phi(D, s) + (t * D + r) * dphi(D, s));
+}
+
+// dF[p,p] += sum over amplitudes of w * dDelta/df_pp: +1 per hole index equal to p, -1 per
+// particle index equal to p.  One workgroup per orbital p, summed in a fixed order.
+__global__ void __launch_bounds__(kThreads)
+flow_fock_kernel(const double* __restrict__ t1, const double* __restrict__ t2, const double* __restrict__ r1,
+                 const double* __restrict__ r2, const double* __restrict__ l1, const double* __restrict__ l2,
+                 const double* __restrict__ eps, int nc, int na, int nv, double s, double* __restrict__ df) {
+  const int nh = nc + na, np = na + nv, n = nc + na + nv;
+  const int p = blockIdx.x;
+  const long pp = (long)np * np;
+  double acc = 0.0;
+  auto w1 = [&](int k, int c) {
+    if (k >= nc && c < na) return 0.0;
+    const long i = (long)k * np + c;
+    return flow_weight(l1[i], t1[i], r1[i], eps[k] - eps[nc + c], s);
+  };
+  auto w2 = [&](int k, int l, int c, int d) {
+    if (k >= nc && l >= nc && c < na && d < na) return 0.0;
+    const long i = (((long)k * nh + l) * np + c) * np + d;
+    return flow_weight(l2[i], t2[i], r2[i], eps[k] + eps[l] - eps[nc + c] - eps[nc + d], s);
+  };
+  if (p < nh) {
+    for (long i = threadIdx.x; i < np; i += blockDim.x) acc += w1(p, (int)i);
+    for (long i = threadIdx.x; i < (long)nh * pp; i += blockDim.x) {
+      const int l = (int)(i / pp), c = (int)((i / np) % np), d = (int)(i % np);
+      acc += w2(p, l, c, d) + w2(l, p, c, d);
+    }
+  }
+  if (p >= nc) {
+    const int c = p - nc;
+    for (long i = threadIdx.x; i < nh; i += blockDim.x) acc -= w1((int)i, c);
+    for (long i = threadIdx.x; i < (long)nh * nh * np; i += blockDim.x) {
+      const int k = (int)(i / ((long)nh * np)), l = (int)((i / np) % nh), e = (int)(i % np);
+      acc -= w2(k, l, c, e) + w2(k, l, e, c);
+    }
+  }
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) df[(long)p * n + p] += acc;
 }
 
 __global__ void diag_kernel(const double* __restrict__ f, int n, double* __restrict__ eps) {
@@ -470,7 +591,40 @@ hipError_t fill(double* p, long n, double v, hipStream_t st) {
 hipError_t symmetrize_pairs(double* x, int nh, int np, hipStream_t st) {
   const long n = (long)nh * nh * np * np;
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(symmetrize_kernel, dim3(blocks_for(n)), dim3(kThreads), 0, st, x, nh, np);
+  hipLaunchKernelGGL(symmetrize_kernel, dim3(blocks_for(n)), dim3(kThreads), 0, st, x, nh, np, 1.0);
+  return hipGetLastError();
+}
+
+hipError_t symmetrize_pairs_scaled(double* x, int nh, int np, double scale, hipStream_t st) {
+  const long n = (long)nh * nh * np * np;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(symmetrize_kernel, dim3(blocks_for(n)), dim3(kThreads), 0, st, x, nh, np, scale);
+  return hipGetLastError();
+}
+
+hipError_t lambda_update(double* l1, double* l2, const double* g1, const double* g2, const double* j1,
+                         const double* j2, const double* eps, int nc, int na, int nv, double s, double* partial,
+                         double* norm2, hipStream_t st) {
+  hipLaunchKernelGGL(lambda_kernel, dim3(kRedBlocks), dim3(kThreads), 0, st, l1, l2, g1, g2, j1, j2, eps, nc, na, nv,
+                     s, partial);
+  hipLaunchKernelGGL(finish_sum, dim3(1), dim3(kThreads), 0, st, partial, kRedBlocks, 1.0, norm2, 0);
+  return hipGetLastError();
+}
+
+hipError_t flow_scale(const double* l1, const double* l2, const double* eps, int nc, int na, int nv, double s,
+                      double* o1, double* o2, hipStream_t st) {
+  const long n = (long)(nc + na) * (na + nv) * (1 + (long)(nc + na) * (na + nv));
+  hipLaunchKernelGGL(flow_scale_kernel, dim3(blocks_for(n)), dim3(kThreads), 0, st, l1, l2, eps, nc, na, nv, s, o1,
+                     o2);
+  return hipGetLastError();
+}
+
+hipError_t flow_fock_gradient(const double* t1, const double* t2, const double* r1, const double* r2,
+                              const double* l1, const double* l2, const double* eps, int nc, int na, int nv,
+                              double s, double* df, hipStream_t st) {
+  const int n = nc + na + nv;
+  hipLaunchKernelGGL(flow_fock_kernel, dim3(n), dim3(kThreads), 0, st, t1, t2, r1, r2, l1, l2, eps, nc, na, nv, s,
+                     df);
   return hipGetLastError();
 }
 

@@ -13,6 +13,7 @@
 #include <fstream>
 #include <functional>
 #include <map>
+#include <set>
 #include <memory>
 #include <sstream>
 #include <stdexcept>
@@ -100,13 +101,15 @@ struct Opd {
   std::vector<int> lab;
 };
 
-enum Kind { K_ZERO, K_ALLOC, K_FREE, K_CONTRACT, K_CONTRACT0, K_ADD, K_DFC, K_SYMM, K_LADDER, K_MASK };
+enum Kind {
+  K_ZERO, K_ALLOC, K_FREE, K_CONTRACT, K_CONTRACT0, K_ADD, K_DFC, K_SYMM, K_LADDER, K_MASK, K_SYMHALF, K_LADDERGRAD
+};
 
 struct Op {
   Kind kind;
   double alpha = 1.0;
   std::vector<Opd> o;
-  int slot = -1;
+  int slot = -1, slot2 = -1, slot3 = -1;
   std::vector<Rng> decl;  // for ALLOC
 };
 
@@ -197,11 +200,11 @@ struct ric_ctx {
   std::vector<std::string> plan_lines;
   std::vector<Slot> slots;
   std::unordered_map<std::string, int> slot_of;
-  std::vector<Op> residual_ops, energy_ops;
+  std::map<std::string, std::vector<Op>> sections;  // residual, energy, adjoint_t, adjoint_theta, energy_grad
 
   // owned device tensors
   DevBuf f, eps, B, BT, BT32, g1, g2, g3, ga, ea, l2, k2, l3, k3, I4, I3, IJ, IK, tau, Edev, red, e0;
-  DevBuf scrA, scrB, scrC, scrC2, scrK, wbuf, wbuf2, lad32, dfa, dfb, dfz;
+  DevBuf scrA, scrB, scrC, scrC2, scrK, wbuf, wbuf2, lad32, dfa, dfb, dfz, lgx, lgt, lgb, xr1, xl;
   Pool pool;
   int precision = RIC_FP64;
   double ladder_ms = 0.0, total_ms = 0.0;
@@ -210,7 +213,7 @@ struct ric_ctx {
 
   ~ric_ctx() {
     for (DevBuf* b : {&f, &eps, &B, &BT, &BT32, &g1, &g2, &g3, &ga, &ea, &l2, &k2, &l3, &k3, &I4, &I3, &IJ, &IK,
-                      &tau, &Edev, &red, &e0, &scrA, &scrB, &scrC, &scrC2, &scrK, &wbuf, &wbuf2, &lad32, &dfa, &dfb, &dfz})
+                      &tau, &Edev, &red, &e0, &scrA, &scrB, &scrC, &scrC2, &scrK, &wbuf, &wbuf2, &lad32, &dfa, &dfb, &dfz, &lgx, &lgt, &lgb, &xr1, &xl})
       b->release();
     pool.release();
     for (auto& e : ev)
@@ -267,7 +270,8 @@ struct ric_ctx {
     const D fixed[] = {{"f", "GG"},     {"B", "XGG"},    {"T1", "HP"},   {"T2", "HHPP"}, {"gA", "AA"},
                        {"eA", "AA"},    {"K2", "AAAA"},  {"K3", "AAAAAA"}, {"I4", "HHHH"}, {"I3", "HHHP"},
                        {"IJ", "HHPP"},  {"IK", "HPHP"},  {"R1", "HP"},   {"R2", "HHPP"}, {"TAU", "HHPP"},
-                       {"E", ""}};
+                       {"E", ""},       {"XR1", "HP"},   {"XL", "HHPP"}, {"YL", "HHPP"}, {"dT1", "HP"},
+                       {"dT2", "HHPP"}, {"dF", "GG"},    {"dB", "XGG"}};
     for (auto& d : fixed) {
       auto v = decl(d.r);
       slot(d.n, &v);
@@ -282,7 +286,7 @@ struct ric_ctx {
       while (ss >> w) t.push_back(w);
       if (t.empty()) continue;
       if (t[0] == "SECTION") {
-        cur = t.at(1) == "residual" ? &residual_ops : &energy_ops;
+        cur = &sections[t.at(1)];
         continue;
       }
       if (t[0] == "END") {
@@ -319,16 +323,29 @@ struct ric_ctx {
       } else if (t[0] == "SYMMETRIZE") {
         op.kind = K_SYMM;
         op.slot = slot(t.at(1));
+      } else if (t[0] == "SYMHALF") {
+        op.kind = K_SYMHALF;
+        op.slot = slot(t.at(1));
       } else if (t[0] == "LADDER") {
-        op.kind = K_LADDER;
+        op.kind = K_LADDER;  // LADDER out in: out += (ce|df) in
+        op.slot = slot(t.at(1));
+        op.slot2 = slot(t.at(2));
+      } else if (t[0] == "LADDERGRAD") {
+        op.kind = K_LADDERGRAD;  // LADDERGRAD dB x tau
+        op.slot = slot(t.at(1));
+        op.slot2 = slot(t.at(2));
+        op.slot3 = slot(t.at(3));
       } else if (t[0] == "MASK") {
-        op.kind = K_MASK;
+        op.kind = K_MASK;  // MASK singles doubles
+        op.slot = slot(t.at(1));
+        op.slot2 = slot(t.at(2));
       } else {
         throw Err(RIC_E_PLAN, "unknown plan operation " + t[0]);
       }
       cur->push_back(op);
     }
-    if (residual_ops.empty()) throw Err(RIC_E_PLAN, "plan has no residual section");
+    for (const char* need : {"residual", "energy", "adjoint_t", "adjoint_theta", "energy_grad"})
+      if (sections.find(need) == sections.end()) throw Err(RIC_E_PLAN, std::string("plan has no section ") + need);
   }
 
   // -- views ------------------------------------------------------------------------------
@@ -779,6 +796,98 @@ struct ric_ctx {
     }
   }
 
+  // -- ladder part of d<x, r>/dB -------------------------------------------------------------
+  // With V[c,e,d,f] = sum_kl x[k,l,c,d] tau[k,l,e,f] (x, tau pair-symmetric, so V[c,e,d,f] =
+  // V[d,f,c,e]): dB[X,c,e] += 2 sum_{d,f} V[c,e,d,f] B[X,d,f] over c, d, e, f in P.  V is built
+  // for a chunk of c at a time and never stored whole.
+  void laddergrad(double* dB, const double* x, const double* taus) {
+    const long np_ = sz.na + sz.nv, nh = sz.nc + sz.na, nx = sz.naux, n = sz.ext(RG), nc = sz.nc;
+    if (np_ == 0 || nh == 0) return;
+    const long pp = np_ * np_, hh = nh * nh;
+    lgx.ensure((size_t)pp * hh);
+    lgt.ensure((size_t)pp * hh);
+    lgb.ensure((size_t)nx * pp);
+    // [k][l][c][d] -> [(c,d)][(k,l)]
+    auto pair_major = [&](const double* in, double* out) {
+      Iter it;
+      it.nd = 4;
+      const long ex[4] = {np_, np_, nh, nh}, so[4] = {np_ * hh, hh, nh, 1}, si[4] = {np_, 1, nh * pp, pp};
+      it.total = pp * hh;
+      for (int i = 0; i < 4; ++i) {
+        it.ext[i] = ex[i];
+        it.so[i] = so[i];
+        it.si[i] = si[i];
+      }
+      HIPCHK(ric::strided_copy(it, 1.0, in, 0.0, out, stream));
+    };
+    pair_major(x, lgx.p);
+    pair_major(taus, lgt.p);
+    {  // B[X][P][P] contiguous over (d,f)
+      Iter it;
+      it.nd = 3;
+      const long ex[3] = {nx, np_, np_}, so[3] = {pp, np_, 1}, si[3] = {n * n, n, 1};
+      it.total = nx * pp;
+      for (int i = 0; i < 3; ++i) {
+        it.ext[i] = ex[i];
+        it.so[i] = so[i];
+        it.si[i] = si[i];
+      }
+      HIPCHK(ric::strided_copy(it, 1.0, B.p + nc * n + nc, 0.0, lgb.p, stream));
+    }
+    long chunk = std::max<long>(1, (long)(1.4e9 / ((double)np_ * pp)));
+    chunk = std::min(chunk, np_);
+    wbuf.ensure((size_t)chunk * np_ * pp);
+    wbuf2.ensure((size_t)chunk * np_ * pp);
+    scrC.ensure((size_t)chunk * np_ * nx);
+    scrK.ensure(64L * 1024 * 1024);
+    for (long c0 = 0; c0 < np_; c0 += chunk) {
+      const long rows = std::min(chunk, np_ - c0);
+      GemmArgs g1;  // V1[(c,d)][(e,f)]
+      g1.M = (int)(rows * np_);
+      g1.N = (int)pp;
+      g1.K = (int)hh;
+      g1.lda = hh;
+      g1.ldb = hh;
+      g1.C = wbuf2.p;
+      g1.ldc = pp;
+      HIPCHK(ric::gemm_nt_f64(g1, lgx.p + c0 * np_ * hh, lgt.p, stream, scrK.p, scrK.n));
+      {  // V2[(c,e)][(d,f)] <- V1[(c,d)][(e,f)]
+        Iter it;
+        it.nd = 4;
+        const long ex[4] = {rows, np_, np_, np_}, so[4] = {np_ * pp, pp, np_, 1}, si[4] = {np_ * pp, np_, pp, 1};
+        it.total = rows * np_ * pp;
+        for (int i = 0; i < 4; ++i) {
+          it.ext[i] = ex[i];
+          it.so[i] = so[i];
+          it.si[i] = si[i];
+        }
+        HIPCHK(ric::strided_copy(it, 1.0, wbuf2.p, 0.0, wbuf.p, stream));
+      }
+      GemmArgs g2;  // C[(c,e)][X] = 2 V2 . Bpp^T
+      g2.M = (int)(rows * np_);
+      g2.N = (int)nx;
+      g2.K = (int)pp;
+      g2.alpha = 2.0;
+      g2.lda = pp;
+      g2.ldb = pp;
+      g2.C = scrC.p;
+      g2.ldc = nx;
+      HIPCHK(ric::gemm_nt_f64(g2, wbuf.p, lgb.p, stream, scrK.p, scrK.n));
+      {  // dB[X][nc + c][nc + e] += C[(c,e)][X]
+        Iter it;
+        it.nd = 3;
+        const long ex[3] = {nx, rows, np_}, so[3] = {n * n, n, 1}, si[3] = {1, np_ * nx, nx};
+        it.total = nx * rows * np_;
+        for (int i = 0; i < 3; ++i) {
+          it.ext[i] = ex[i];
+          it.so[i] = so[i];
+          it.si[i] = si[i];
+        }
+        HIPCHK(ric::strided_copy(it, 1.0, scrC.p, 1.0, dB + (nc + c0) * n + nc, stream));
+      }
+    }
+  }
+
   // -- plan execution -----------------------------------------------------------------------
   // RIC_PROFILE=1: per-operation-kind device time (synchronizes after every operation)
   bool profile = getenv("RIC_PROFILE") != nullptr;
@@ -786,7 +895,7 @@ struct ric_ctx {
 
   // RIC_PROGRESS=1: one stderr line when each expensive phase of a plan section ends
   bool progress = getenv("RIC_PROGRESS") != nullptr;
-  bool warmed = false;
+  std::set<const std::vector<Op>*> warmed;
 
   // populate the intermediate pool with every size the plan allocates (no kernels)
   void warm_pool(std::vector<Op>& ops) {
@@ -802,10 +911,9 @@ struct ric_ctx {
   }
 
   void run(std::vector<Op>& ops) {
-    if (!warmed) {
-      warm_pool(residual_ops);
-      warm_pool(energy_ops);
-      warmed = true;
+    if (!warmed.count(&ops)) {  // first run of this section: its intermediates enter the pool
+      warm_pool(ops);
+      warmed.insert(&ops);
     }
     hipEvent_t pa = nullptr, pb = nullptr;
     auto t_start = std::chrono::steady_clock::now();
@@ -816,7 +924,7 @@ struct ric_ctx {
       HIPCHK(hipEventCreate(&pb));
     }
     static const char* kname[] = {"ZERO", "ALLOC", "FREE", "CONTRACT", "CONTRACT0", "ADD", "DFC", "SYMM",
-                                  "LADDER", "MASK"};
+                                  "LADDER", "MASK", "SYMHALF", "LADDERGRAD"};
     for (Op& op : ops) {
       if (profile) HIPCHK(hipEventRecord(pa, stream));
       switch (op.kind) {
@@ -850,15 +958,21 @@ struct ric_ctx {
         case K_SYMM:
           HIPCHK(ric::symmetrize_pairs(slots[op.slot].ptr, sz.nc + sz.na, sz.na + sz.nv, stream));
           break;
+        case K_SYMHALF:
+          HIPCHK(ric::symmetrize_pairs_scaled(slots[op.slot].ptr, sz.nc + sz.na, sz.na + sz.nv, 0.5, stream));
+          break;
         case K_LADDER: {
           HIPCHK(hipEventRecord(ev[0], stream));
-          ladder(slots[slot_of["TAU"]].ptr, slots[slot_of["R2"]].ptr);
+          ladder(slots[op.slot2].ptr, slots[op.slot].ptr);
           HIPCHK(hipEventRecord(ev[1], stream));
           ladder_ran = true;
           break;
         }
+        case K_LADDERGRAD:
+          laddergrad(slots[op.slot].ptr, slots[op.slot2].ptr, slots[op.slot3].ptr);
+          break;
         case K_MASK:
-          HIPCHK(ric::mask_active(slots[slot_of["R1"]].ptr, slots[slot_of["R2"]].ptr, sz.nc, sz.na, sz.nv, stream));
+          HIPCHK(ric::mask_active(slots[op.slot].ptr, slots[op.slot2].ptr, sz.nc, sz.na, sz.nv, stream));
           break;
       }
       if (progress && (op.kind == K_LADDER || op.kind == K_DFC ||
@@ -900,7 +1014,8 @@ struct ric_ctx {
   }
 
   static const char* kind_name(Kind k) {
-    static const char* n[] = {"ZERO", "ALLOC", "FREE", "CONTRACT", "CONTRACT0", "ADD", "DFC", "SYMM", "LADDER", "MASK"};
+    static const char* n[] = {"ZERO", "ALLOC", "FREE", "CONTRACT", "CONTRACT0", "ADD", "DFC", "SYMM",
+                              "LADDER", "MASK", "SYMHALF", "LADDERGRAD"};
     return n[k];
   }
 
@@ -1105,7 +1220,7 @@ int ric_residual(ric_ctx* ctx, const double* T1, const double* T2, double* R1, d
     ctx->bind("R2", R2);
     ctx->ladder_ran = false;
     HIPCHK(hipEventRecord(ctx->ev[2], ctx->stream));
-    ctx->run(ctx->residual_ops);
+    ctx->run(ctx->sections.at("residual"));
     HIPCHK(hipEventRecord(ctx->ev[3], ctx->stream));
     HIPCHK(hipEventSynchronize(ctx->ev[3]));
     float ms = 0.f;
@@ -1145,7 +1260,7 @@ int ric_energy(ric_ctx* ctx, const double* T1, const double* T2, double* e_corr,
     ctx->bind("E", ctx->Edev.p);
     ctx->precision = RIC_FP64;
     HIPCHK(ric::fill(ctx->Edev.p, 1, 0.0, ctx->stream));
-    ctx->run(ctx->energy_ops);
+    ctx->run(ctx->sections.at("energy"));
     if (e0) {
       const double* g1 = ctx->sz.na ? ctx->g1.p : nullptr;
       const double* g2 = ctx->sz.na ? ctx->g2.p : nullptr;
@@ -1175,6 +1290,95 @@ int ric_ladder(ric_ctx* ctx, const double* tau, double* R2, int precision) {
     HIPCHK(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
     ctx->ladder_ms = ms;
     ctx->total_ms = ms;
+  });
+}
+
+int ric_adjoint_residual(ric_ctx* ctx, const double* T1, const double* T2, const double* X1, const double* X2,
+                         double* dT1, double* dT2, double* dF, double* dB) {
+  return guard(ctx, [&] {
+    ctx->require_loaded();
+    if (!T1 || !T2 || !X1 || !X2 || !dT1 || !dT2) throw Err(RIC_E_ARG, "null amplitude/cotangent pointer");
+    if ((dF == nullptr) != (dB == nullptr)) throw Err(RIC_E_ARG, "dF and dB must both be given or both be NULL");
+    const long nh = ctx->sz.nc + ctx->sz.na, np_ = ctx->sz.na + ctx->sz.nv;
+    const long n1 = nh * np_, n2 = n1 * n1;
+    ctx->precision = RIC_FP64;
+    // cotangents of the masked residuals: R1 as given, R2 through its pair-symmetric part
+    ctx->xr1.ensure(n1);
+    ctx->xl.ensure(n2);
+    HIPCHK(hipMemcpyAsync(ctx->xr1.p, X1, n1 * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->xl.p, X2, n2 * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(ric::symmetrize_pairs_scaled(ctx->xl.p, (int)nh, (int)np_, 0.5, ctx->stream));
+    HIPCHK(ric::mask_active(ctx->xr1.p, ctx->xl.p, ctx->sz.nc, ctx->sz.na, ctx->sz.nv, ctx->stream));
+    ctx->bind("T1", T1);
+    ctx->bind("T2", T2);
+    ctx->bind("XR1", ctx->xr1.p);
+    ctx->bind("XL", ctx->xl.p);
+    ctx->bind("dT1", dT1);
+    ctx->bind("dT2", dT2);
+    ctx->run(ctx->sections.at("adjoint_t"));
+    if (dF) {
+      ctx->bind("dF", dF);
+      ctx->bind("dB", dB);
+      ctx->run(ctx->sections.at("adjoint_theta"));
+    }
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+  });
+}
+
+int ric_energy_gradient(ric_ctx* ctx, const double* T1, const double* T2, double* dT1, double* dT2, double* dF,
+                        double* dB) {
+  return guard(ctx, [&] {
+    ctx->require_loaded();
+    if (!T1 || !T2 || !dT1 || !dT2 || !dF || !dB) throw Err(RIC_E_ARG, "null pointer");
+    ctx->precision = RIC_FP64;
+    ctx->bind("T1", T1);
+    ctx->bind("T2", T2);
+    ctx->bind("dT1", dT1);
+    ctx->bind("dT2", dT2);
+    ctx->bind("dF", dF);
+    ctx->bind("dB", dB);
+    ctx->run(ctx->sections.at("energy_grad"));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+  });
+}
+
+int ric_lambda_update(ric_ctx* ctx, double* L1, double* L2, const double* G1, const double* G2, const double* J1,
+                      const double* J2, double s, double* step_norm2) {
+  return guard(ctx, [&] {
+    ctx->require_loaded();
+    if (!L1 || !L2 || !G1 || !G2 || !J1 || !J2) throw Err(RIC_E_ARG, "null pointer");
+    if (!(s >= 0.0)) throw Err(RIC_E_ARG, "flow parameter must be >= 0");
+    ctx->red.ensure(1024);
+    ctx->Edev.ensure(4);
+    HIPCHK(ric::lambda_update(L1, L2, G1, G2, J1, J2, ctx->eps.p, ctx->sz.nc, ctx->sz.na, ctx->sz.nv, s, ctx->red.p,
+                              ctx->Edev.p + 3, ctx->stream));
+    double v = 0.0;
+    HIPCHK(hipMemcpyAsync(&v, ctx->Edev.p + 3, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (!std::isfinite(v)) throw Err(RIC_E_NONFINITE, "non-finite Lagrangian step");
+    if (step_norm2) *step_norm2 = v;
+  });
+}
+
+int ric_flow_scale(ric_ctx* ctx, const double* L1, const double* L2, double s, double* O1, double* O2) {
+  return guard(ctx, [&] {
+    ctx->require_loaded();
+    if (!L1 || !L2 || !O1 || !O2) throw Err(RIC_E_ARG, "null pointer");
+    if (!(s >= 0.0)) throw Err(RIC_E_ARG, "flow parameter must be >= 0");
+    HIPCHK(ric::flow_scale(L1, L2, ctx->eps.p, ctx->sz.nc, ctx->sz.na, ctx->sz.nv, s, O1, O2, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+  });
+}
+
+int ric_flow_fock_gradient(ric_ctx* ctx, const double* T1, const double* T2, const double* R1, const double* R2,
+                           const double* L1, const double* L2, double s, double* dF) {
+  return guard(ctx, [&] {
+    ctx->require_loaded();
+    if (!T1 || !T2 || !R1 || !R2 || !L1 || !L2 || !dF) throw Err(RIC_E_ARG, "null pointer");
+    if (!(s >= 0.0)) throw Err(RIC_E_ARG, "flow parameter must be >= 0");
+    HIPCHK(ric::flow_fock_gradient(T1, T2, R1, R2, L1, L2, ctx->eps.p, ctx->sz.nc, ctx->sz.na, ctx->sz.nv, s, dF,
+                                   ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
   });
 }
 

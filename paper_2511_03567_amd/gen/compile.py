@@ -49,6 +49,10 @@ DECL = {
     "gA": (A, A), "eA": (A, A), "K2": (A,) * 4, "K3": (A,) * 6,
     "I4": (H, H, H, H), "I3": (H, H, H, P), "IJ": (H, H, P, P), "IK": (H, P, H, P),
     "R1": (H, P), "R2": (H, H, P, P), "TAU": (H, H, P, P),
+    # adjoint sections: cotangents, the ladder applied to XL, and gradient outputs
+    "XR1": (H, P), "XL": (H, H, P, P), "YL": (H, H, P, P),
+    "dT1": (H, P), "dT2": (H, H, P, P), "dF": (G, G), "dB": (X, G, G),
+    "dI4": (H, H, H, H), "dI3": (H, H, H, P), "dIJ": (H, H, P, P), "dIK": (H, P, H, P),
 }
 
 
@@ -277,30 +281,33 @@ def _is_ladder(ops, ext, rng):
     return None
 
 
-def compile_plan(e_terms, r1_terms, s2_terms):
-    plan = Plan()
-    groups = OrderedDict()     # key -> list of (coef, term ops...)
-    ladder = []
-    direct = []
+class _Terms:
+    """Terms of one plan section, sorted into the emission strategies."""
 
-    dfgroups = OrderedDict()
-    dfterms = []
+    def __init__(self):
+        self.groups = OrderedDict()     # sum-before-contract groups
+        self.dfterms = []               # terms with an integral over >= 3 particle indices
+        self.direct = []
+        self.ladder = []                # (coef, rest, (k, l, e, f), rng): R2 += (ce|df) rest[k,l,e,f]
 
-    def handle(t: SFTerm, target, out_ranges):
+    def add_sf(self, t: SFTerm, target, out_ranges, allow_ladder=True):
         ops = factor_operands(t)
         rng = _rng_of(ops, t.ext, out_ranges)
-        ext = t.ext
-        if target == "R2":
-            lad = _is_ladder(ops, ext, rng)
+        if target == "R2" and allow_ladder:
+            lad = _is_ladder(ops, t.ext, rng)
             if lad is not None:
-                ladder.append((t.coef, lad[0], lad[1], rng))
+                self.ladder.append((t.coef, lad[0], lad[1], rng))
                 return
+        self.add_ops(target, t.coef, t.ext, out_ranges, ops, rng)
+
+    def add_ops(self, target, coef, ext, out_ranges, ops, rng):
+        ext = tuple(ext)
         bs = [o for o in ops if o.name == "B"]
-        if bs:
-            dfterms.append((target, t.coef, ext, out_ranges, ops, rng))
+        if len(bs) == 2:
+            self.dfterms.append((target, coef, ext, out_ranges, ops, rng))
             return
         if len(ops) == 1:
-            direct.append((target, t.coef, ext, out_ranges, ops, rng))
+            self.direct.append((target, coef, ext, out_ranges, ops, rng))
             return
         # sum-before-contract: the last contraction pairs one stored operand P0 with an
         # intermediate Y of the others; pick the P0 with the cheapest total, preferring T2
@@ -317,7 +324,7 @@ def compile_plan(e_terms, r1_terms, s2_terms):
                 ys, yf, Yo = greedy_tree(rest, keep, rng)
             fl_last, _, _ = _pair_cost(ops[big], Yo, set(ext), rng)
             cost = yf + 2.0 * fl_last
-            pref = 0 if ops[big].name == "T2" else 1
+            pref = 0 if ops[big].name in ("T2", "XL", "YL") else 1
             cand = (cost > 1.5 * gflops + 1e6, pref, cost)
             if choice is None or cand < choice[0]:
                 choice = (cand, big, ys, yf, Yo)
@@ -339,30 +346,41 @@ def compile_plan(e_terms, r1_terms, s2_terms):
             g_rng = {l: (rng[l] if l in p0_ext else _widen(rng[l])) for l in rng}
             key = (target, P0.name, tuple(g_rng[l] for l in P0.labels), tuple(ren[l] for l in P0.labels),
                    tuple(g_rng[l] for l in ext), tuple((ren[l], g_rng[l]) for l in ylabs))
-            groups.setdefault(key, []).append((t.coef, ysteps, Yop, ylabs, P0, ext, out_ranges, rng, ren, g_rng))
+            self.groups.setdefault(key, []).append((coef, ysteps, Yop, ylabs, P0, ext, out_ranges, rng, ren, g_rng))
         else:
-            direct.append((target, t.coef, ext, out_ranges, ops, rng))
+            self.direct.append((target, coef, ext, out_ranges, ops, rng))
 
+    def emit(self, plan):
+        _emit_groups(plan, self.groups)
+        _emit_df_terms(plan, self.dfterms)
+        _emit_direct(plan, self.direct)
+
+
+def _emit_tau(plan, ladder):
+    """tau = sum of the ladder terms' amplitude products, then tau + tau^T(pairs)."""
+    plan.lines.append("ALLOC TAU HHPP")
+    plan.lines.append("ZERO TAU")
+    for coef, rest, (k, l, e, f), rng in ladder:
+        out = Operand("TAU", (rng[k], rng[l], rng[e], rng[f]), (k, l, e, f))
+        _emit_into(plan, coef, rest, out, rng)
+    plan.lines.append("SYMMETRIZE TAU")
+
+
+def compile_plan(e_terms, r1_terms, s2_terms, adjoint=True):
+    plan = Plan()
+    res = _Terms()
     for t in r1_terms:
-        handle(t, "R1", (t.rng[t.ext[0]], t.rng[t.ext[1]]))
+        res.add_sf(t, "R1", (t.rng[t.ext[0]], t.rng[t.ext[1]]))
     for t in s2_terms:
-        handle(t, "R2", tuple(t.rng[l] for l in t.ext))
-    res_lines_start = len(plan.lines)
+        res.add_sf(t, "R2", tuple(t.rng[l] for l in t.ext))
     plan.lines.append("SECTION residual")
     plan.lines.append("ZERO R1")
     plan.lines.append("ZERO R2")
-    _emit_groups(plan, groups)
-    _emit_df_terms(plan, dfterms)
-    _emit_direct(plan, direct)
+    res.emit(plan)
     plan.lines.append("SYMMETRIZE R2")
     # ladder: tau accumulated, symmetrized over pairs, contracted with (ce|df) from B
-    if ladder:
-        plan.lines.append("ALLOC TAU HHPP")
-        plan.lines.append("ZERO TAU")
-        for coef, rest, (k, l, e, f), rng in ladder:
-            out = Operand("TAU", (rng[k], rng[l], rng[e], rng[f]), (k, l, e, f))
-            _emit_into(plan, coef, rest, out, rng)
-        plan.lines.append("SYMMETRIZE TAU")
+    if res.ladder:
+        _emit_tau(plan, res.ladder)
         plan.lines.append("LADDER R2 TAU")
         nP, nH, nx = extent(P), extent(H), extent(X)
         plan.ladder_flops = nP * nP * (nP + 1) / 2 * nP * nx * 2 + nH * nH * nP * (nP + 1) / 2 * nP * nP * 2
@@ -374,16 +392,139 @@ def compile_plan(e_terms, r1_terms, s2_terms):
     # energy: every term is a full contraction
     plan.lines.append("SECTION energy")
     plan.lines.append("ZERO E")
-    groups.clear()
-    dfterms.clear()
-    direct.clear()
+    en = _Terms()
     for t in e_terms:
-        handle(t, "E", ())
-    _emit_groups(plan, groups)
-    _emit_df_terms(plan, dfterms)
-    _emit_direct(plan, direct)
+        en.add_sf(t, "E", ())
+    en.emit(plan)
     plan.lines.append("END")
+    if adjoint:
+        compile_adjoint(plan, e_terms, r1_terms, s2_terms, res.ladder)
     return plan, res_flops
+
+
+# ---- adjoint sections -----------------------------------------------------------------------
+#
+# With x = (XR1, XL) the cotangents of the masked residuals (XL pair-symmetric), the
+# residual section computes R1 = mask(S1), R2 = mask(S2 + S2^T + W.(tau + tau^T)),
+# W[c,d,e,f] = (ce|df).  Its vector-Jacobian products:
+#   cotangent of S1 = XR1;  of S2 = 2 XL;  of tau = 2 YL with YL = W.XL (the ladder applied to XL);
+#   dB from the ladder: 2 sum_{d,f} V[c,e,d,f] B[X,d,f], V[c,e,d,f] = sum_kl XL[k,l,c,d] tau_s[k,l,e,f].
+# Each term coef * prod(ops) of a section contributes, for every differentiable operand o,
+#   d<o>[o.labels] += coef * (cotangent) * prod(other operands),
+# compiled with the same strategies as the forward terms.  Stored integral blocks
+# I = sum_X B B collect dI first, and dI is contracted with B at the end of a section.
+
+_GRAD = {"T1": "dT1", "T2": "dT2", "f": "dF", "B": "dB", "I4": "dI4", "I3": "dI3", "IJ": "dIJ", "IK": "dIK"}
+_AMPS = ("T1", "T2")
+_THETA = ("f", "B", "I4", "I3", "IJ", "IK")
+_IBLOCKS = {"I4": (H, H, H, H), "I3": (H, H, H, P), "IJ": (H, H, P, P), "IK": (H, P, H, P)}
+
+
+def _derivatives(terms: _Terms, target, coef, ext, out_ranges, ops, rng, cot, wrt):
+    for i, o in enumerate(ops):
+        if o.name not in wrt:
+            continue
+        if len(set(o.labels)) != len(o.labels):
+            raise ValueError(f"repeated label in a differentiated operand {o.text()}")
+        rest = ([cot] if cot is not None else []) + [x for j, x in enumerate(ops) if j != i]
+        if not rest:
+            raise ValueError("constant derivative term")
+        terms.add_ops(_GRAD[o.name], coef, o.labels, o.ranges, rest, rng)
+
+
+def _cotangent(target, ext, rng):
+    if target == "R1":
+        return Operand("XR1", [rng[l] for l in ext], ext), 1
+    if target == "R2":
+        return Operand("XL", [rng[l] for l in ext], ext), 2
+    return None, 1
+
+
+def _emit_dI_to_dB(plan):
+    """dB[X,p,r] += sum_qs dI[p,r,q,s] B[X,q,s] and dB[X,q,s] += sum_pr dI[p,r,q,s] B[X,p,r]."""
+    for name, (r0, r1, r2, r3) in _IBLOCKS.items():
+        d = Operand("d" + name, (r0, r1, r2, r3), ("0", "1", "2", "3"))
+        plan.contract(Operand("dB", (X, r0, r1), ("X0", "0", "1")), 1, d, Operand("B", (X, r2, r3), ("X0", "2", "3")))
+        plan.contract(Operand("dB", (X, r2, r3), ("X0", "2", "3")), 1, d, Operand("B", (X, r0, r1), ("X0", "0", "1")))
+
+
+def compile_adjoint(plan, e_terms, r1_terms, s2_terms, ladder):
+    # d/dT of <x, r>: the products J_r^T x used by the Lagrangian iteration
+    tt = _Terms()
+    for target, terms in (("R1", r1_terms), ("R2", s2_terms)):
+        for t in terms:
+            ops = factor_operands(t)
+            out_ranges = tuple(t.rng[l] for l in t.ext)
+            rng = _rng_of(ops, t.ext, out_ranges)
+            if target == "R2" and _is_ladder(ops, t.ext, rng) is not None:
+                continue
+            cot, w = _cotangent(target, t.ext, rng)
+            _derivatives(tt, target, t.coef * w, t.ext, out_ranges, ops, rng, cot, _AMPS)
+    for coef, rest, (k, l, e, f), rng in ladder:
+        if any(o.name not in _AMPS for o in rest):
+            raise ValueError("ladder amplitude products must hold amplitudes only")
+        cot = Operand("YL", (rng[k], rng[l], rng[e], rng[f]), (k, l, e, f))
+        _derivatives(tt, "R2", coef * 2, (k, l, e, f), None, rest, rng, cot, _AMPS)
+    plan.lines.append("SECTION adjoint_t")
+    plan.lines.append("ZERO dT1")
+    plan.lines.append("ZERO dT2")
+    if ladder:
+        plan.lines.append("ALLOC YL HHPP")
+        plan.lines.append("ZERO YL")
+        plan.lines.append("LADDER YL XL")
+    tt.emit(plan)
+    if ladder:
+        plan.lines.append("FREE YL")
+    plan.lines.append("SYMHALF dT2")
+    plan.lines.append("MASK dT1 dT2")
+    plan.lines.append("END")
+
+    # d/d(f, B) of <x, r>
+    th = _Terms()
+    for target, terms in (("R1", r1_terms), ("R2", s2_terms)):
+        for t in terms:
+            ops = factor_operands(t)
+            out_ranges = tuple(t.rng[l] for l in t.ext)
+            rng = _rng_of(ops, t.ext, out_ranges)
+            if target == "R2" and _is_ladder(ops, t.ext, rng) is not None:
+                continue
+            cot, w = _cotangent(target, t.ext, rng)
+            _derivatives(th, target, t.coef * w, t.ext, out_ranges, ops, rng, cot, _THETA)
+    plan.lines.append("SECTION adjoint_theta")
+    plan.lines.append("ZERO dF")
+    plan.lines.append("ZERO dB")
+    for name, rr in _IBLOCKS.items():
+        plan.lines.append(f"ALLOC d{name} {''.join(RN[r] for r in rr)}")
+        plan.lines.append(f"ZERO d{name}")
+    th.emit(plan)
+    if ladder:
+        _emit_tau(plan, ladder)
+        plan.lines.append("LADDERGRAD dB XL TAU")
+        plan.lines.append("FREE TAU")
+    _emit_dI_to_dB(plan)
+    for name in _IBLOCKS:
+        plan.lines.append(f"FREE d{name}")
+    plan.lines.append("END")
+
+    # gradient of the energy functional with respect to T, f and B
+    eg = _Terms()
+    for t in e_terms:
+        ops = factor_operands(t)
+        rng = _rng_of(ops, t.ext, ())
+        _derivatives(eg, "E", t.coef, (), (), ops, rng, None, _AMPS + _THETA)
+    plan.lines.append("SECTION energy_grad")
+    for name in ("dT1", "dT2", "dF", "dB"):
+        plan.lines.append(f"ZERO {name}")
+    for name, rr in _IBLOCKS.items():
+        plan.lines.append(f"ALLOC d{name} {''.join(RN[r] for r in rr)}")
+        plan.lines.append(f"ZERO d{name}")
+    eg.emit(plan)
+    _emit_dI_to_dB(plan)
+    for name in _IBLOCKS:
+        plan.lines.append(f"FREE d{name}")
+    plan.lines.append("SYMHALF dT2")
+    plan.lines.append("MASK dT1 dT2")
+    plan.lines.append("END")
 
 
 def _emit_steps(plan, steps, final_out=None, alpha=1):

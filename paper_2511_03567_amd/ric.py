@@ -54,10 +54,17 @@ def library():
     lib.ric_energy.argtypes = [P, P, P, ctypes.POINTER(D), ctypes.POINTER(D)]
     lib.ric_ladder.argtypes = [P, P, P, I]
     lib.ric_last_timings.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(D)]
+    lib.ric_adjoint_residual.argtypes = [P] * 9
+    lib.ric_energy_gradient.argtypes = [P] * 7
+    lib.ric_lambda_update.argtypes = [P] * 7 + [D, ctypes.POINTER(D)]
+    lib.ric_flow_scale.argtypes = [P, P, P, D, P, P]
+    lib.ric_flow_fock_gradient.argtypes = [P] * 7 + [D, P]
     lib.ric_last_error.argtypes = [P]
     lib.ric_last_error.restype = ctypes.c_char_p
     for fn in ("ric_create", "ric_set_spaces", "ric_load_fock", "ric_load_df", "ric_load_rdms",
-               "ric_residual", "ric_update", "ric_energy", "ric_ladder", "ric_last_timings"):
+               "ric_residual", "ric_update", "ric_energy", "ric_ladder", "ric_last_timings",
+               "ric_adjoint_residual", "ric_energy_gradient", "ric_lambda_update", "ric_flow_scale",
+               "ric_flow_fock_gradient"):
         getattr(lib, fn).restype = I
     _lib = lib
     return lib
@@ -157,6 +164,41 @@ class Context:
         _, s2 = self.amplitude_shapes()
         self._check(self.lib.ric_ladder(self.h, _ptr(tau, s2, "tau"), _ptr(R2, s2, "R2"), int(precision)))
 
+    # --- adjoint -----------------------------------------------------------------------
+    def adjoint_residual(self, T1, T2, X1, X2, dT1, dT2, dF=None, dB=None):
+        """dT = (dr/dT)^T x; with dF, dB also (dr/df)^T x and (dr/dB)^T x."""
+        s1, s2 = self.amplitude_shapes()
+        n, nx = self.n, self.sizes[3]
+        self._check(self.lib.ric_adjoint_residual(
+            self.h, _ptr(T1, s1, "T1"), _ptr(T2, s2, "T2"), _ptr(X1, s1, "X1"), _ptr(X2, s2, "X2"),
+            _ptr(dT1, s1, "dT1"), _ptr(dT2, s2, "dT2"), _ptr(dF, (n, n), "dF"), _ptr(dB, (nx, n, n), "dB")))
+
+    def energy_gradient(self, T1, T2, dT1, dT2, dF, dB):
+        s1, s2 = self.amplitude_shapes()
+        n, nx = self.n, self.sizes[3]
+        self._check(self.lib.ric_energy_gradient(
+            self.h, _ptr(T1, s1, "T1"), _ptr(T2, s2, "T2"), _ptr(dT1, s1, "dT1"), _ptr(dT2, s2, "dT2"),
+            _ptr(dF, (n, n), "dF"), _ptr(dB, (nx, n, n), "dB")))
+
+    def lambda_update(self, L1, L2, G1, G2, J1, J2, s):
+        s1, s2 = self.amplitude_shapes()
+        out = ctypes.c_double()
+        self._check(self.lib.ric_lambda_update(
+            self.h, _ptr(L1, s1, "L1"), _ptr(L2, s2, "L2"), _ptr(G1, s1, "G1"), _ptr(G2, s2, "G2"),
+            _ptr(J1, s1, "J1"), _ptr(J2, s2, "J2"), float(s), ctypes.byref(out)))
+        return out.value
+
+    def flow_scale(self, L1, L2, s, O1, O2):
+        s1, s2 = self.amplitude_shapes()
+        self._check(self.lib.ric_flow_scale(self.h, _ptr(L1, s1, "L1"), _ptr(L2, s2, "L2"), float(s),
+                                            _ptr(O1, s1, "O1"), _ptr(O2, s2, "O2")))
+
+    def flow_fock_gradient(self, T1, T2, R1, R2, L1, L2, s, dF):
+        s1, s2 = self.amplitude_shapes()
+        self._check(self.lib.ric_flow_fock_gradient(
+            self.h, _ptr(T1, s1, "T1"), _ptr(T2, s2, "T2"), _ptr(R1, s1, "R1"), _ptr(R2, s2, "R2"),
+            _ptr(L1, s1, "L1"), _ptr(L2, s2, "L2"), float(s), _ptr(dF, (self.n, self.n), "dF")))
+
     def timings(self):
         a = ctypes.c_double()
         b = ctypes.c_double()
@@ -204,3 +246,76 @@ def solve(ctx: Context, s, tol=1e-8, max_iter=200, precision=RIC_FP64, polish_to
             return e, e0, T1, T2, it
         prev = step
     raise RicError(RIC_E_NOCONV, f"regularized iteration did not converge in {max_iter} iterations")
+
+
+def solve_lambda(ctx: Context, T1, T2, s, tol=1e-10, max_iter=400, log=None):
+    """Lagrange multipliers of the converged regularized iteration.
+
+    Iterates L <- dE/dT + Delta phi L + J_r^T(phi L) from L = dE/dT until the step norm
+    falls below tol.  Returns (L1, L2, dE/df at fixed T, dE/dB at fixed T, iterations).
+    """
+    s1, s2 = ctx.amplitude_shapes()
+    n, nx = ctx.n, ctx.sizes[3]
+    dev = T1.device
+    z = lambda sh: torch.zeros(sh, dtype=torch.float64, device=dev)
+    G1, G2, eF, eB = z(s1), z(s2), z((n, n)), z((nx, n, n))
+    ctx.energy_gradient(T1, T2, G1, G2, eF, eB)
+    L1, L2 = G1.clone(), G2.clone()
+    P1, P2, J1, J2 = z(s1), z(s2), z(s1), z(s2)
+    for it in range(1, max_iter + 1):
+        ctx.flow_scale(L1, L2, s, P1, P2)
+        ctx.adjoint_residual(T1, T2, P1, P2, J1, J2)
+        step = ctx.lambda_update(L1, L2, G1, G2, J1, J2, s) ** 0.5
+        if log is not None:
+            log.append({"iter": it, "step": step})
+        if step < tol:
+            return L1, L2, eF, eB, it
+    raise RicError(RIC_E_NOCONV, f"Lagrangian iteration did not converge in {max_iter} iterations")
+
+
+def energy_gradient(ctx: Context, T1, T2, s, tol=1e-10, max_iter=400):
+    """dE_corr/df and dE_corr/dB at the converged amplitudes T1, T2 (flow parameter s)."""
+    L1, L2, dF, dB, _ = solve_lambda(ctx, T1, T2, s, tol, max_iter)
+    s1, s2 = ctx.amplitude_shapes()
+    dev = T1.device
+    P1 = torch.zeros(s1, dtype=torch.float64, device=dev)
+    P2 = torch.zeros(s2, dtype=torch.float64, device=dev)
+    ctx.flow_scale(L1, L2, s, P1, P2)
+    J1, J2 = torch.empty_like(P1), torch.empty_like(P2)
+    rF, rB = torch.empty_like(dF), torch.empty_like(dB)
+    ctx.adjoint_residual(T1, T2, P1, P2, J1, J2, rF, rB)
+    R1, R2 = torch.empty_like(P1), torch.empty_like(P2)
+    ctx.residual(T1, T2, R1, R2)
+    dF.add_(rF)
+    dB.add_(rB)
+    ctx.flow_fock_gradient(T1, T2, R1, R2, L1, L2, s, dF)
+    return dF, dB
+
+
+class RICEnergy(torch.autograd.Function):
+    """E_corr(f, B) of the converged spin-free RIC-MRCCSD iteration, differentiable in f and B.
+
+    forward(f, B, ctx, s, tol): loads f and B into the context (whose spaces and RDMs are
+    set), solves the regularized iteration and returns E_corr as a 0-d tensor.  backward
+    solves the Lagrange multipliers and returns dE/df and dE/dB; the particle-particle
+    ladder is regenerated from B in both directions.
+    """
+
+    @staticmethod
+    def forward(fctx, f, B, ctx: Context, s: float, tol: float = 1e-10):
+        f = f.detach().contiguous()
+        B = B.detach().contiguous()
+        ctx.load_fock(f)
+        ctx.load_df(B)
+        e, _, T1, T2, _ = solve(ctx, s, tol=tol)
+        fctx.ric = (ctx, s, tol, T1, T2, f, B)
+        return torch.tensor(e, dtype=torch.float64, device=f.device)
+
+    @staticmethod
+    def backward(fctx, grad):
+        ctx, s, tol, T1, T2, f, B = fctx.ric
+        ctx.load_fock(f)     # the context may have been used for other inputs since forward
+        ctx.load_df(B)
+        dF, dB = energy_gradient(ctx, T1, T2, s, tol)
+        g = grad.to(dF.dtype)
+        return g * dF, g * dB, None, None, None

@@ -31,6 +31,8 @@ DECL = {
     "f": "GG", "B": "XGG", "T1": "HP", "T2": "HHPP", "gA": "AA", "eA": "AA", "K2": "AAAA",
     "K3": "AAAAAA", "I4": "HHHH", "I3": "HHHP", "IJ": "HHPP", "IK": "HPHP",
     "R1": "HP", "R2": "HHPP", "TAU": "HHPP", "E": "",
+    "XR1": "HP", "XL": "HHPP", "YL": "HHPP", "dT1": "HP", "dT2": "HHPP", "dF": "GG", "dB": "XGG",
+    "dI4": "HHHH", "dI3": "HHHP", "dIJ": "HHPP", "dIK": "HPHP",
 }
 
 
@@ -146,15 +148,24 @@ class Interpreter:
             elif op == "SYMMETRIZE":
                 x = T[tok[1]]
                 x[...] = x + x.transpose(1, 0, 3, 2)
+            elif op == "SYMHALF":
+                x = T[tok[1]]
+                x[...] = 0.5 * (x + x.transpose(1, 0, 3, 2))
             elif op == "LADDER":
                 nc = self.nc
                 Bp = T["B"][:, nc:, nc:]
                 W = np.einsum("xce,xdf->cedf", Bp, Bp)
                 T[tok[1]] += np.einsum("cedf,klef->klcd", W, T[tok[2]], optimize=True)
+            elif op == "LADDERGRAD":
+                # dB[X,c,e] += 2 sum_{d,f} V[c,e,d,f] B[X,d,f],  V = sum_kl XL[k,l,c,d] tau[k,l,e,f]
+                nc = self.nc
+                Bp = T["B"][:, nc:, nc:]
+                V = np.einsum("klcd,klef->cedf", T[tok[2]], T[tok[3]], optimize=True)
+                T[tok[1]][:, nc:, nc:] += 2.0 * np.einsum("cedf,xdf->xce", V, Bp, optimize=True)
             elif op == "MASK":
                 nc, na = self.nc, self.na
-                T["R1"][nc:, :na] = 0.0
-                T["R2"][nc:, nc:, :na, :na] = 0.0
+                T[tok[1]][nc:, :na] = 0.0
+                T[tok[2]][nc:, nc:, :na, :na] = 0.0
             else:
                 raise ValueError(op)
         return T

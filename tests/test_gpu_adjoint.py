@@ -1,0 +1,141 @@
+"""GPU adjoint through the C ABI.
+
+1. Vector-Jacobian products of the residual and the energy gradient at fixed T against
+   central differences of the oracle (exact up to rounding: the residual and energy are
+   polynomials of degree two in T and B and linear in f): dot-product tests
+   <x, J v> = <J^T x, v> to 1e-9 relative.
+2. The full derivative of the converged E_corr with respect to f and B (Lagrange
+   multipliers of the regularized fixed point, eq. ric-update) against central finite
+   differences of converged GPU solves, h = 1e-5, on seeded symmetric directions.
+"""
+import numpy as np
+import pytest
+
+import synthetic as S
+from oracle import ricmrcc as R
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+H = 1e-3
+
+
+def _ctx(cfg, f, B, inp):
+    from paper_2511_03567_amd import ric
+    dev = torch.device("cuda", 0)
+    ctx = ric.Context(0)
+    ctx.set_spaces(cfg.nc, cfg.na, cfg.nv, cfg.naux)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    ctx.load_fock(t(f))
+    ctx.load_df(t(B))
+    if cfg.na:
+        ctx.load_rdms(t(inp.G1), t(inp.G2), t(inp.G3))
+    else:
+        ctx.load_rdms(None, None, None)
+    return ctx, t
+
+
+def _sym2(rng, nH, nP, m2, scale=1.0):
+    x = rng.standard_normal((nH, nH, nP, nP)) * scale
+    return 0.5 * (x + x.transpose(1, 0, 3, 2)) * m2
+
+
+def _dot(a, b):
+    return float(sum(np.sum(p * q) for p, q in zip(a, b)))
+
+
+CASES = [(2, 4, 10, 48, 1), (1, 2, 3, 7, 2), (3, 0, 6, 11, 3), (0, 3, 4, 9, 4), (3, 4, 20, 30, 5)]
+
+
+@pytest.mark.parametrize("nc,na,nv,naux,seed", CASES)
+def test_vjp_and_energy_gradient_match_oracle_derivatives(nc, na, nv, naux, seed):
+    print(f"adjoint dot-product test nc={nc} na={na} nv={nv} naux={naux}", flush=True)
+    cfg = S.custom_config("adj", nc, na, nv, naux, seed)
+    inp = S.make_inputs(cfg)
+    nH, nP, n = nc + na, na + nv, nc + na + nv
+    rng = np.random.default_rng(seed + 200)
+    m1, m2 = R.block_mask(nc, na, nv)
+    T = (rng.standard_normal((nH, nP)) * 0.05 * m1, _sym2(rng, nH, nP, m2, 0.05))
+    x = (rng.standard_normal((nH, nP)) * m1, _sym2(rng, nH, nP, m2))
+    v = (rng.standard_normal((nH, nP)) * m1, _sym2(rng, nH, nP, m2))
+    df = rng.standard_normal((n, n))
+    df = df + df.T
+    dB = rng.standard_normal((naux, n, n))
+    dB = dB + dB.transpose(0, 2, 1)
+    G = (inp.G1, inp.G2, inp.G3)
+    ctx, t = _ctx(cfg, inp.f, inp.B, inp)
+    z = lambda *sh: torch.zeros(sh, dtype=torch.float64, device="cuda")
+    gT1, gT2 = t(T[0]), t(T[1])
+    dT1, dT2, dF, dBg = z(nH, nP), z(nH, nH, nP, nP), z(n, n), z(naux, n, n)
+    ctx.adjoint_residual(gT1, gT2, t(x[0]), t(x[1]), dT1, dT2, dF, dBg)
+    eT1, eT2, eF, eB = z(nH, nP), z(nH, nH, nP, nP), z(n, n), z(naux, n, n)
+    ctx.energy_gradient(gT1, gT2, eT1, eT2, eF, eB)
+    got = [_dot((dT1.cpu().numpy(), dT2.cpu().numpy()), v), float(np.sum(dF.cpu().numpy() * df)),
+           float(np.sum(dBg.cpu().numpy() * dB)), _dot((eT1.cpu().numpy(), eT2.cpu().numpy()), v),
+           float(np.sum(eF.cpu().numpy() * df)), float(np.sum(eB.cpu().numpy() * dB))]
+    ref = lambda f, B: R.Reference(nc, na, nv, f, B, *G)
+    r0 = ref(inp.f, inp.B)
+    jt = [(a - b) / (2 * H) for a, b in zip(r0.residual(T[0] + H * v[0], T[1] + H * v[1]),
+                                            r0.residual(T[0] - H * v[0], T[1] - H * v[1]))]
+    rfp, rfm = ref(inp.f + H * df, inp.B), ref(inp.f - H * df, inp.B)
+    rbp, rbm = ref(inp.f, inp.B + H * dB), ref(inp.f, inp.B - H * dB)
+    jf = [(a - b) / (2 * H) for a, b in zip(rfp.residual(*T), rfm.residual(*T))]
+    jb = [(a - b) / (2 * H) for a, b in zip(rbp.residual(*T), rbm.residual(*T))]
+    want = [_dot(x, jt), _dot(x, jf), _dot(x, jb),
+            (r0.energy(T[0] + H * v[0], T[1] + H * v[1]) - r0.energy(T[0] - H * v[0], T[1] - H * v[1])) / (2 * H),
+            (rfp.energy(*T) - rfm.energy(*T)) / (2 * H), (rbp.energy(*T) - rbm.energy(*T)) / (2 * H)]
+    for name, g, w in zip(("J^T x . v", "dr/df", "dr/dB", "dE/dT", "dE/df", "dE/dB"), got, want):
+        print(f"  {name}: {g:.12e} vs {w:.12e}", flush=True)
+        assert abs(g - w) <= 1e-9 * max(1.0, abs(w)), name
+    d2 = dT2.cpu().numpy()
+    assert np.array_equal(d2, d2.transpose(1, 0, 3, 2))
+    assert np.all(d2[nc:, nc:, :na, :na] == 0.0)
+
+
+def _solve_energy(cfg, inp, f, B, s, tol):
+    from paper_2511_03567_amd import ric
+    ctx, _ = _ctx(cfg, f, B, inp)
+    e, _, _, _, _ = ric.solve(ctx, s, tol=tol, max_iter=400)
+    return e
+
+
+@pytest.mark.parametrize("name,cfg,ndir", [("tiny CAS(4,4)", S.CONFIGS["tiny_cas44"], 20),
+                                           ("CAS(6,6) nc6 nv60 naux180", S.CONFIGS["adjoint_cas66"], 4)])
+def test_total_gradient_matches_finite_differences(name, cfg, ndir):
+    """dE_corr/d(f, B) of the converged solve (Lagrangian) vs central differences of solves."""
+    from paper_2511_03567_amd import ric
+    print(f"total gradient {name}", flush=True)
+    inp = S.make_inputs(cfg)
+    s, tol, h = cfg.s, 1e-13, 1e-5
+    ctx, t = _ctx(cfg, inp.f, inp.B, inp)
+    _, _, T1, T2, _ = ric.solve(ctx, s, tol=tol, max_iter=400)
+    dF, dB = ric.energy_gradient(ctx, T1, T2, s, tol=1e-12)
+    dF, dB = dF.cpu().numpy(), dB.cpu().numpy()
+    rng = np.random.default_rng(77)
+    n, nx = cfg.n, cfg.naux
+    for k in range(ndir):
+        df = rng.standard_normal((n, n)) * 1e-2
+        df = df + df.T
+        dBd = rng.standard_normal((nx, n, n)) * 1e-2 / np.sqrt(nx)
+        dBd = dBd + dBd.transpose(0, 2, 1)
+        ep = _solve_energy(cfg, inp, inp.f + h * df, inp.B + h * dBd, s, tol)
+        em = _solve_energy(cfg, inp, inp.f - h * df, inp.B - h * dBd, s, tol)
+        fd = (ep - em) / (2 * h)
+        an = float(np.sum(dF * df) + np.sum(dB * dBd))
+        print(f"  direction {k}: analytic {an:.10e}  finite difference {fd:.10e}", flush=True)
+        assert abs(an - fd) <= 1e-6 * max(abs(fd), 1e-3)
+
+
+def test_autograd_function():
+    from paper_2511_03567_amd import ric
+    cfg = S.CONFIGS["tiny_cas44"]
+    inp = S.make_inputs(cfg)
+    ctx, t = _ctx(cfg, inp.f, inp.B, inp)
+    f = t(inp.f).requires_grad_(True)
+    B = t(inp.B).requires_grad_(True)
+    e = ric.RICEnergy.apply(f, B, ctx, cfg.s, 1e-12)
+    gf, gB = torch.autograd.grad(e, (f, B))
+    _, _, T1, T2, _ = ric.solve(ctx, cfg.s, tol=1e-12)
+    dF, dB = ric.energy_gradient(ctx, T1, T2, cfg.s, tol=1e-12)
+    assert torch.allclose(gf, dF, rtol=1e-8, atol=1e-12)
+    assert torch.allclose(gB, dB, rtol=1e-8, atol=1e-12)
