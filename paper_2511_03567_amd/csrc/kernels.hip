@@ -26,21 +26,23 @@ inline int blocks_for(long n, int per = kThreads) {
 // ---- strided views ------------------------------------------------------------------
 
 // out[o(i)] = beta * out[o(i)] + alpha * in[s(i)] over the iteration space of `it`
-template <typename TO, typename TI>
+// Idx: unsigned 32-bit index arithmetic when the space has fewer than 2^32 elements (its
+// divisions are far cheaper than 64-bit ones), else 64-bit.
+template <typename TO, typename TI, typename Idx>
 __global__ void __launch_bounds__(kThreads)
 strided_axpby(Iter it, double alpha, const TI* __restrict__ in, double beta, TO* __restrict__ out) {
   const long total = it.total;
   for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
-    long rem = t;
+    Idx rem = (Idx)t;
     long so = 0, si = 0;
 #pragma unroll
     for (int d = kMaxDims - 1; d >= 0; --d) {
       if (d < it.nd) {
-        const long e = it.ext[d];
-        const long x = rem % e;
+        const Idx e = (Idx)it.ext[d];
+        const Idx x = rem % e;
         rem /= e;
-        so += x * it.so[d];
-        si += x * it.si[d];
+        so += (long)x * it.so[d];
+        si += (long)x * it.si[d];
       }
     }
     const double v = alpha * (double)in[si];
@@ -561,25 +563,28 @@ __global__ void ladder_scatter_pm(const double* __restrict__ sp, const double* _
 
 // ---- launchers ------------------------------------------------------------------------------
 
-hipError_t strided_copy(const Iter& it, double alpha, const double* in, double beta, double* out, hipStream_t st) {
+template <typename TO, typename TI>
+hipError_t launch_strided(const Iter& it, double alpha, const TI* in, double beta, TO* out, hipStream_t st) {
   if (it.total <= 0) return hipSuccess;
-  hipLaunchKernelGGL((strided_axpby<double, double>), dim3(blocks_for(it.total)), dim3(kThreads), 0, st, it,
-                     alpha, in, beta, out);
+  if (it.total < (1L << 32))
+    hipLaunchKernelGGL((strided_axpby<TO, TI, unsigned>), dim3(blocks_for(it.total)), dim3(kThreads), 0, st, it,
+                       alpha, in, beta, out);
+  else
+    hipLaunchKernelGGL((strided_axpby<TO, TI, unsigned long>), dim3(blocks_for(it.total)), dim3(kThreads), 0, st,
+                       it, alpha, in, beta, out);
   return hipGetLastError();
+}
+
+hipError_t strided_copy(const Iter& it, double alpha, const double* in, double beta, double* out, hipStream_t st) {
+  return launch_strided<double, double>(it, alpha, in, beta, out, st);
 }
 
 hipError_t strided_copy_f32(const Iter& it, double alpha, const double* in, float* out, hipStream_t st) {
-  if (it.total <= 0) return hipSuccess;
-  hipLaunchKernelGGL((strided_axpby<float, double>), dim3(blocks_for(it.total)), dim3(kThreads), 0, st, it,
-                     alpha, in, 0.0, out);
-  return hipGetLastError();
+  return launch_strided<float, double>(it, alpha, in, 0.0, out, st);
 }
 
 hipError_t strided_copy_f32f32(const Iter& it, const float* in, float* out, hipStream_t st) {
-  if (it.total <= 0) return hipSuccess;
-  hipLaunchKernelGGL((strided_axpby<float, float>), dim3(blocks_for(it.total)), dim3(kThreads), 0, st, it, 1.0,
-                     in, 0.0, out);
-  return hipGetLastError();
+  return launch_strided<float, float>(it, 1.0, in, 0.0, out, st);
 }
 
 hipError_t fill(double* p, long n, double v, hipStream_t st) {

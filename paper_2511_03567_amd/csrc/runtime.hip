@@ -102,7 +102,8 @@ struct Opd {
 };
 
 enum Kind {
-  K_ZERO, K_ALLOC, K_FREE, K_CONTRACT, K_CONTRACT0, K_ADD, K_DFC, K_SYMM, K_LADDER, K_MASK, K_SYMHALF, K_LADDERGRAD
+  K_ZERO, K_ALLOC, K_FREE, K_CONTRACT, K_CONTRACT0, K_ADD, K_DFC, K_SYMM, K_LADDER, K_MASK, K_SYMHALF, K_LADDERGRAD,
+  K_LOOP, K_ENDLOOP
 };
 
 struct Op {
@@ -110,7 +111,9 @@ struct Op {
   double alpha = 1.0;
   std::vector<Opd> o;
   int slot = -1, slot2 = -1, slot3 = -1;
+  bool chunked = false;   // ALLOC/FREE/ZERO of the slot a LOOP chunks
   std::vector<Rng> decl;  // for ALLOC
+  std::string text;       // the plan line (for RIC_PROFILE=2)
 };
 
 struct Slot {
@@ -175,9 +178,24 @@ struct Pool {
       return p;
     }
     double* p = nullptr;
-    HIPCHK(hipMalloc(&p, elems * sizeof(double)));
+    if (hipMalloc(&p, elems * sizeof(double)) != hipSuccess) {
+      // out of device memory: give back the idle blocks of other sizes and try once more
+      (void)hipGetLastError();
+      release_idle();
+      HIPCHK(hipMalloc(&p, elems * sizeof(double)));
+    }
     all_.push_back({p, elems});
     return p;
+  }
+  // free the blocks no intermediate holds (the next ALLOC of their size allocates again)
+  void release_idle() {
+    (void)hipDeviceSynchronize();  // queued kernels may still read blocks returned to the pool
+    for (auto& kv : free_) {
+      (void)hipFree(kv.second);
+      all_.erase(std::find_if(all_.begin(), all_.end(),
+                              [&](const std::pair<double*, size_t>& a) { return a.first == kv.second; }));
+    }
+    free_.clear();
   }
   void put(double* p, size_t elems) { free_.insert({std::max<size_t>(elems, 1), p}); }
   void release() {
@@ -278,6 +296,8 @@ struct ric_ctx {
     }
     std::string line;
     std::vector<Op>* cur = nullptr;
+    std::vector<size_t> loops;  // open LOOP operations of the current section
+    int loop_slot = -1;
     while (std::getline(in, line)) {
       if (line.empty() || line[0] == '#') continue;
       std::stringstream ss(line);
@@ -290,11 +310,13 @@ struct ric_ctx {
         continue;
       }
       if (t[0] == "END") {
+        if (!loops.empty()) throw Err(RIC_E_PLAN, "LOOP without ENDLOOP");
         cur = nullptr;
         continue;
       }
       if (!cur) throw Err(RIC_E_PLAN, "operation outside a section: " + line);
       Op op;
+      const bool in_loop = !loops.empty();
       std::map<std::string, int> labels;
       if (t[0] == "ALLOC") {
         op.kind = K_ALLOC;
@@ -339,9 +361,27 @@ struct ric_ctx {
         op.kind = K_MASK;  // MASK singles doubles
         op.slot = slot(t.at(1));
         op.slot2 = slot(t.at(2));
+      } else if (t[0] == "LOOP") {
+        // LOOP name dim: the body runs once per chunk of dimension dim of intermediate name
+        if (!loops.empty()) throw Err(RIC_E_PLAN, "nested LOOP");
+        op.kind = K_LOOP;
+        op.slot = slot(t.at(1));
+        op.slot2 = std::stoi(t.at(2));
+        if (op.slot2 != 0) throw Err(RIC_E_PLAN, "LOOP chunks the leading dimension only");
+        loops.push_back(cur->size());
+        loop_slot = op.slot;
+      } else if (t[0] == "ENDLOOP") {
+        if (loops.empty()) throw Err(RIC_E_PLAN, "ENDLOOP without LOOP");
+        op.kind = K_ENDLOOP;
+        (*cur)[loops.back()].slot3 = (int)cur->size();
+        loops.pop_back();
+        loop_slot = -1;
       } else {
         throw Err(RIC_E_PLAN, "unknown plan operation " + t[0]);
       }
+      if (in_loop && op.slot == loop_slot && (op.kind == K_ALLOC || op.kind == K_FREE || op.kind == K_ZERO))
+        op.chunked = true;
+      if (op.kind == K_CONTRACT || op.kind == K_CONTRACT0 || op.kind == K_DFC) op.text = line;
       cur->push_back(op);
     }
     for (const char* need : {"residual", "energy", "adjoint_t", "adjoint_theta", "energy_grad"})
@@ -736,7 +776,8 @@ struct ric_ctx {
     if (mixed) HIPCHK(ric::pack_tau_f32(taup, nh, np_, tpf, tmf, ldp, ldm, stream));
     else HIPCHK(ric::pack_tau(taup, nh, np_, tpd, tmd, ldp, ldm, stream));
     // chunk of c rows: W'[(c,e)][(d,f)] (one GEMM), then W+/- per (c,d) pair
-    const double budget = 1.4e9;  // elements of W' per chunk
+    // elements of W' per chunk (RIC_LADDER_BUDGET overrides)
+    const double budget = getenv("RIC_LADDER_BUDGET") ? std::atof(getenv("RIC_LADDER_BUDGET")) : 1.4e9;
     long chunk = std::max<long>(1, (long)(budget / ((double)np_ * pp)));
     chunk = std::min<long>(chunk, np_);
     const size_t wel = (size_t)chunk * np_ * pp;
@@ -803,6 +844,7 @@ struct ric_ctx {
   void laddergrad(double* dB, const double* x, const double* taus) {
     const long np_ = sz.na + sz.nv, nh = sz.nc + sz.na, nx = sz.naux, n = sz.ext(RG), nc = sz.nc;
     if (np_ == 0 || nh == 0) return;
+    release_scratch();  // this step needs its own large buffers
     const long pp = np_ * np_, hh = nh * nh;
     lgx.ensure((size_t)pp * hh);
     lgt.ensure((size_t)pp * hh);
@@ -888,18 +930,55 @@ struct ric_ctx {
     }
   }
 
+  // Give back the idle pool blocks and the work buffers (regrown on demand); only between
+  // operations, after the stream has drained.
+  void release_scratch() {
+    HIPCHK(hipStreamSynchronize(stream));
+    pool.release_idle();
+    for (DevBuf* b : {&scrA, &scrB, &scrC, &scrC2, &wbuf, &wbuf2, &dfa, &dfb, &dfz, &lgx, &lgt, &lgb}) b->release();
+  }
+
   // -- plan execution -----------------------------------------------------------------------
   // RIC_PROFILE=1: per-operation-kind device time (synchronizes after every operation)
   bool profile = getenv("RIC_PROFILE") != nullptr;
+  bool profile_ops = profile && std::string(getenv("RIC_PROFILE")) == "2";  // also each operation over 20 ms
   std::map<std::string, std::pair<double, long>> prof;
 
   // RIC_PROGRESS=1: one stderr line when each expensive phase of a plan section ends
   bool progress = getenv("RIC_PROGRESS") != nullptr;
   std::set<const std::vector<Op>*> warmed;
 
+  // chunked execution of a LOOP body: the intermediate's leading index runs over [s, s + len)
+  // elements of one chunk of the intermediate (RIC_LOOP_BUDGET overrides, e.g. to test many chunks)
+  double loop_budget = getenv("RIC_LOOP_BUDGET") ? std::atof(getenv("RIC_LOOP_BUDGET")) : 1.5e9;
+  struct Loop {
+    bool on = false;
+    int slot = -1;
+    long n = 0, s = 0, len = 0, lenmax = 0, rest = 1;
+    double* buf = nullptr;
+  } loop;
+
+  // Inside a LOOP: the label that the chunked intermediate carries in its leading dimension is
+  // restricted to the current chunk in every operand of the operation.
+  void restrict_to_chunk(const Op& op, View* v, int nv) {
+    if (!loop.on) return;
+    int lab = -1;
+    for (size_t k = 0; k < op.o.size(); ++k)
+      if (op.o[k].slot == loop.slot) lab = op.o[k].lab.at(0);
+    if (lab < 0) return;
+    for (int k = 0; k < nv; ++k) {
+      const int d = v[k].find(lab);
+      if (d < 0) continue;
+      if (v[k].ext[d] != loop.n) throw Err(RIC_E_PLAN, "chunked label does not span its full range");
+      if (v[k].p) v[k].p += loop.s * v[k].str[d];
+      v[k].ext[d] = loop.len;
+    }
+  }
+
   // populate the intermediate pool with every size the plan allocates (no kernels)
   void warm_pool(std::vector<Op>& ops) {
     for (Op& op : ops) {
+      if (op.chunked) continue;
       if (op.kind == K_ALLOC) {
         slots[op.slot].decl = op.decl;
         slots[op.slot].ptr = pool.get((size_t)slot_elems(op.slot));
@@ -924,36 +1003,55 @@ struct ric_ctx {
       HIPCHK(hipEventCreate(&pb));
     }
     static const char* kname[] = {"ZERO", "ALLOC", "FREE", "CONTRACT", "CONTRACT0", "ADD", "DFC", "SYMM",
-                                  "LADDER", "MASK", "SYMHALF", "LADDERGRAD"};
-    for (Op& op : ops) {
+                                  "LADDER", "MASK", "SYMHALF", "LADDERGRAD", "LOOP", "ENDLOOP"};
+    auto step = [&](Op& op) {
       if (profile) HIPCHK(hipEventRecord(pa, stream));
       switch (op.kind) {
         case K_ALLOC: {
           Slot& s = slots[op.slot];
           s.decl = op.decl;
-          s.ptr = pool.get((size_t)slot_elems(op.slot));
+          if (op.chunked) {
+            loop.buf = pool.get((size_t)(loop.lenmax * loop.rest));
+            s.ptr = loop.buf - loop.s * loop.rest;  // leading index i lives at buf + (i - s) * rest
+          } else {
+            s.ptr = pool.get((size_t)slot_elems(op.slot));
+          }
           break;
         }
         case K_FREE: {
           Slot& s = slots[op.slot];
-          pool.put(s.ptr, (size_t)slot_elems(op.slot));
+          if (op.chunked) pool.put(loop.buf, (size_t)(loop.lenmax * loop.rest));
+          else pool.put(s.ptr, (size_t)slot_elems(op.slot));
           s.ptr = nullptr;
           break;
         }
         case K_ZERO: {
           Slot& s = slots[op.slot];
-          HIPCHK(ric::fill(s.ptr, slot_elems(op.slot), 0.0, stream));
+          if (op.chunked) HIPCHK(ric::fill(loop.buf, loop.len * loop.rest, 0.0, stream));
+          else HIPCHK(ric::fill(s.ptr, slot_elems(op.slot), 0.0, stream));
           break;
         }
         case K_CONTRACT:
-        case K_CONTRACT0:
-          contract(view(op.o[0]), op.alpha, view(op.o[1]), view(op.o[2]), op.kind == K_CONTRACT0, true);
+        case K_CONTRACT0: {
+          View v[3] = {view(op.o[0]), view(op.o[1]), view(op.o[2])};
+          restrict_to_chunk(op, v, 3);
+          contract(v[0], op.alpha, v[1], v[2], op.kind == K_CONTRACT0, true);
           break;
-        case K_ADD:
-          axpby(view(op.o[0]), op.alpha, view(op.o[1]), 1.0);
+        }
+        case K_ADD: {
+          View v[2] = {view(op.o[0]), view(op.o[1])};
+          restrict_to_chunk(op, v, 2);
+          axpby(v[0], op.alpha, v[1], 1.0);
           break;
-        case K_DFC:
-          dfc(view(op.o[0]), op.alpha, view(op.o[1]), view(op.o[2]), view(op.o[3]));
+        }
+        case K_DFC: {
+          View v[4] = {view(op.o[0]), view(op.o[1]), view(op.o[2]), view(op.o[3])};
+          restrict_to_chunk(op, v, 4);
+          dfc(v[0], op.alpha, v[1], v[2], v[3]);
+          break;
+        }
+        case K_LOOP:
+        case K_ENDLOOP:
           break;
         case K_SYMM:
           HIPCHK(ric::symmetrize_pairs(slots[op.slot].ptr, sz.nc + sz.na, sz.na + sz.nv, stream));
@@ -975,13 +1073,13 @@ struct ric_ctx {
           HIPCHK(ric::mask_active(slots[op.slot].ptr, slots[op.slot2].ptr, sz.nc, sz.na, sz.nv, stream));
           break;
       }
-      if (progress && (op.kind == K_LADDER || op.kind == K_DFC ||
+      if (progress && (op.kind == K_LADDER || op.kind == K_LADDERGRAD || op.kind == K_DFC ||
                        ((op.kind == K_CONTRACT || op.kind == K_CONTRACT0) && op_flops(op) > 5e13))) {
         // report after the operation has finished on the device
         HIPCHK(hipStreamSynchronize(stream));
         ++big_done;
         const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
-        if (op.kind == K_LADDER || big_done % 16 == 0)
+        if (op.kind == K_LADDER || op.kind == K_LADDERGRAD || big_done % 16 == 0)
           fprintf(stderr, "  [ric] %s done: %d large operations, %.1f s\n", kind_name(op.kind), big_done, el);
       }
       if (profile) {
@@ -1002,7 +1100,35 @@ struct ric_ctx {
         auto& pr = prof[key];
         pr.first += ms;
         pr.second += 1;
+        if (profile_ops && ms > 20.f)
+          fprintf(stderr, "  RIC_OP %9.2f ms %9.2f TF/s  %s\n", ms, op_flops(op) / (ms * 1e-3) / 1e12,
+                  op.text.empty() ? kname[op.kind] : op.text.c_str());
       }
+    };
+    for (size_t oi = 0; oi < ops.size(); ++oi) {
+      Op& op = ops[oi];
+      if (op.kind != K_LOOP) {
+        step(op);
+        continue;
+      }
+      // the body runs once per chunk of the leading dimension of the chunked intermediate
+      const size_t end = (size_t)op.slot3;
+      const auto& decl = slots[op.slot].decl;
+      long n = sz.ext(decl.at(0)), rest = 1;
+      for (size_t d = 1; d < decl.size(); ++d) rest *= sz.ext(decl[d]);
+      const long lenmax = std::min<long>(std::max<long>(n, 1), std::max<long>(1, (long)(loop_budget / std::max<long>(rest, 1))));
+      for (long s0 = 0; s0 < n; s0 += lenmax) {
+        loop.on = true;
+        loop.slot = op.slot;
+        loop.n = n;
+        loop.s = s0;
+        loop.len = std::min(lenmax, n - s0);
+        loop.lenmax = lenmax;
+        loop.rest = rest;
+        for (size_t k = oi + 1; k < end; ++k) step(ops[k]);
+      }
+      loop.on = false;
+      oi = end;
     }
     if (profile) {
       for (auto& kv : prof) fprintf(stderr, "  RIC_PROFILE %-16s %10.3f ms  %6ld ops\n", kv.first.c_str(), kv.second.first,
@@ -1015,7 +1141,7 @@ struct ric_ctx {
 
   static const char* kind_name(Kind k) {
     static const char* n[] = {"ZERO", "ALLOC", "FREE", "CONTRACT", "CONTRACT0", "ADD", "DFC", "SYMM",
-                              "LADDER", "MASK", "SYMHALF", "LADDERGRAD"};
+                              "LADDER", "MASK", "SYMHALF", "LADDERGRAD", "LOOP", "ENDLOOP"};
     return n[k];
   }
 
@@ -1319,6 +1445,7 @@ int ric_adjoint_residual(ric_ctx* ctx, const double* T1, const double* T2, const
     if (dF) {
       ctx->bind("dF", dF);
       ctx->bind("dB", dB);
+      ctx->release_scratch();  // the (f, B) part holds its own, larger intermediates
       ctx->run(ctx->sections.at("adjoint_theta"));
     }
     HIPCHK(hipStreamSynchronize(ctx->stream));

@@ -573,6 +573,35 @@ def _emit_into(plan, coef, ops, out, rng):
     _emit_steps(plan, steps, final_out=out, alpha=coef)
 
 
+ACC_CAP = 2.5e9   # elements (cost-model size) above which a group accumulator is chunked
+
+
+def _vol(ranges):
+    n = 1.0
+    for r in ranges:
+        n *= extent(r)
+    return n
+
+
+def _chunk_role(members, ylabs0, ext0, g0, ren0):
+    """Canonical role of a label of the group's accumulator that every member's block
+    covers over the group's full range, so the group can run per chunk of it (an output
+    label of the final contraction, or one it sums over with the stored operand)."""
+    best = None
+    for l in ylabs0:
+        role, r0 = ren0[l], g0[l]
+        ok = True
+        for m in members:
+            ylabs, rng, ren = m[3], m[7], m[8]
+            lm = [x for x in ylabs if ren.get(x) == role]
+            if len(lm) != 1 or rng[lm[0]] != r0:
+                ok = False
+                break
+        if ok and (best is None or extent(r0) > extent(best[1])):
+            best = (role, r0)
+    return None if best is None else best[0]
+
+
 def _emit_groups(plan, groups):
     for key, members in groups.items():
         target = key[0]
@@ -582,7 +611,21 @@ def _emit_groups(plan, groups):
             out = Operand(target, out_ranges0, ext0)
             plan.contract(out, coef0, P00, Yop0)
             continue
+        # an accumulator too large to hold whole is built and consumed in chunks of an
+        # output label that every member covers over the same range (leading dimension)
+        chunk = None
+        if _vol([g0[l] for l in ylabs0]) > ACC_CAP:
+            chunk = _chunk_role(members, ylabs0, ext0, g0, ren0)
+
+        def order(ylabs, ren):
+            if chunk is None:
+                return list(ylabs)
+            return [l for l in ylabs if ren.get(l) == chunk] + [l for l in ylabs if ren.get(l) != chunk]
+
+        ylabs0 = order(ylabs0, ren0)
         yr = [g0[l] for l in ylabs0]
+        if chunk is not None:
+            plan.lines.append(f"LOOP t{plan.tmp} 0")
         acc = plan.new_tmp(yr)
         plan.lines.append(f"ZERO {acc}")
         # second level: members whose intermediate is one product X * Z of two stored
@@ -618,6 +661,7 @@ def _emit_groups(plan, groups):
                 rest_members.append(items[0][6])
                 continue
             coef0_, X0, Z0, zl0, rng0_, yl0, m0 = items[0]
+            yl0 = order(yl0, m0[8])
             zr = [_widen(rng0_[l]) for l in zl0]
             zacc = plan.new_tmp(zr)
             plan.lines.append(f"ZERO {zacc}")
@@ -631,6 +675,7 @@ def _emit_groups(plan, groups):
             plan.free(zacc)
         for coef, ysteps, Yop, ylabs, P0m, ext, out_ranges, rng, ren, g in rest_members:
             # the member's own (possibly narrower) ranges address a sub-block of acc
+            ylabs = order(ylabs, ren)
             accop = Operand(acc, [rng[l] for l in ylabs], ylabs)
             if not ysteps:
                 plan.add(accop, coef, Yop)
@@ -640,6 +685,8 @@ def _emit_groups(plan, groups):
         P0 = Operand(P00.name, [g0[l] for l in P00.labels], P00.labels)
         plan.contract(out, 1, P0, Operand(acc, yr, ylabs0))
         plan.free(acc)
+        if chunk is not None:
+            plan.lines.append("ENDLOOP")
 
 
 def _nbig(o):

@@ -162,6 +162,8 @@ class Interpreter:
                 Bp = T["B"][:, nc:, nc:]
                 V = np.einsum("klcd,klef->cedf", T[tok[2]], T[tok[3]], optimize=True)
                 T[tok[1]][:, nc:, nc:] += 2.0 * np.einsum("cedf,xdf->xce", V, Bp, optimize=True)
+            elif op in ("LOOP", "ENDLOOP"):
+                pass   # chunking does not change what is computed
             elif op == "MASK":
                 nc, na = self.nc, self.na
                 T[tok[1]][nc:, :na] = 0.0

@@ -139,3 +139,30 @@ def test_autograd_function():
     dF, dB = ric.energy_gradient(ctx, T1, T2, cfg.s, tol=1e-12)
     assert torch.allclose(gf, dF, rtol=1e-8, atol=1e-12)
     assert torch.allclose(gB, dB, rtol=1e-8, atol=1e-12)
+
+
+def test_chunked_accumulators_match_whole(monkeypatch):
+    """Plan groups whose accumulator is built per chunk (LOOP) give the same (f, B) parts
+    when the chunk budget forces many chunks as when one chunk holds everything."""
+    cfg = S.custom_config("chunk", 3, 4, 20, 30, 21)
+    inp = S.make_inputs(cfg)
+    nc, na, nv, naux = cfg.nc, cfg.na, cfg.nv, cfg.naux
+    nH, nP, n = nc + na, na + nv, cfg.n
+    rng = np.random.default_rng(22)
+    m1, m2 = R.block_mask(nc, na, nv)
+    T = (rng.standard_normal((nH, nP)) * 0.05 * m1, _sym2(rng, nH, nP, m2, 0.05))
+    x = (rng.standard_normal((nH, nP)) * m1, _sym2(rng, nH, nP, m2))
+    outs = []
+    for budget in (None, "500"):
+        if budget is None:
+            monkeypatch.delenv("RIC_LOOP_BUDGET", raising=False)
+        else:
+            monkeypatch.setenv("RIC_LOOP_BUDGET", budget)
+        ctx, t = _ctx(cfg, inp.f, inp.B, inp)
+        z = lambda *sh: torch.zeros(sh, dtype=torch.float64, device="cuda")
+        dT1, dT2, dF, dB = z(nH, nP), z(nH, nH, nP, nP), z(n, n), z(naux, n, n)
+        ctx.adjoint_residual(t(T[0]), t(T[1]), t(x[0]), t(x[1]), dT1, dT2, dF, dB)
+        outs.append((dF.cpu().numpy(), dB.cpu().numpy()))
+        ctx.close()
+    for a, b in zip(outs[0], outs[1]):
+        assert np.abs(a - b).max() <= 1e-12 * max(1.0, np.abs(a).max())
