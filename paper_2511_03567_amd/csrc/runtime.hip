@@ -439,18 +439,30 @@ struct ric_ctx {
   }
 
   // gather view dims in the given order into a contiguous buffer
-  void gather(const View& v, const std::vector<int>& order, double* dst, float* dst32) {
+  // dst[order] <- v; with nk > 0 the last nk dimensions of `order` form rows of length kp
+  // (>= their product), the padding zero-filled
+  void gather(const View& v, const std::vector<int>& order, double* dst, float* dst32, size_t nk = 0, long kp = 0) {
     Iter it;
     it.nd = (int)order.size();
     it.total = 1;
-    long st = 1;
+    long st = 1, total = 1;
+    long kprod = 1;
+    for (size_t i = order.size() - nk; i < order.size(); ++i) kprod *= v.ext[order[i]];
+    const bool padded = nk > 0 && kp > kprod;
     for (int i = it.nd - 1; i >= 0; --i) {
       it.ext[i] = v.ext[order[i]];
       it.si[i] = v.str[order[i]];
       it.so[i] = st;
       st *= it.ext[i];
+      total *= it.ext[i];
+      if (padded && i == it.nd - (int)nk) st = kp;  // rows of the padded length
     }
-    it.total = st;
+    it.total = total;
+    if (padded) {
+      const long rows = kprod > 0 ? total / kprod : 0;
+      if (dst32) HIPCHK(ric::fill(reinterpret_cast<double*>(dst32), (rows * kp + 1) / 2, 0.0, stream));
+      else HIPCHK(ric::fill(dst, rows * kp, 0.0, stream));
+    }
     if (dst32) HIPCHK(ric::strided_copy_f32(it, 1.0, v.p, dst32, stream));
     else HIPCHK(ric::strided_copy(it, 1.0, v.p, 0.0, dst, stream));
   }
@@ -473,6 +485,11 @@ struct ric_ctx {
     }
     return true;
   }
+
+  // products above this many flops get K padded to the vector width (RIC_PAD_MIN_FLOPS overrides)
+  double pad_min_flops = getenv("RIC_PAD_MIN_FLOPS") ? std::atof(getenv("RIC_PAD_MIN_FLOPS")) : 1e10;
+  // in RIC_FP32MIX, products above this many flops take fp32 operands (RIC_FP32_MIN_FLOPS overrides)
+  double fp32_min_flops = getenv("RIC_FP32_MIN_FLOPS") ? std::atof(getenv("RIC_FP32_MIN_FLOPS")) : 1e10;
 
   // -- contraction out (+)= alpha * sum a * b -------------------------------------------------
   void contract(const View& out, double alpha, const View& a, const View& b, bool fresh, bool allow32) {
@@ -511,7 +528,7 @@ struct ric_ctx {
       return;
     }
     const double flops = 2.0 * (double)M * N * K;
-    const bool use32 = allow32 && precision == RIC_FP32MIX && flops > 1e10;
+    const bool use32 = allow32 && precision == RIC_FP32MIX && flops > fp32_min_flops;
 
     // energy-type full contraction: dot product
     if (M == 1 && N == 1 && !use32) {
@@ -548,25 +565,34 @@ struct ric_ctx {
     if (directC && M > 1 && N > 1 && sOm < N) directC = false;
     if (M == 1) sOm = N;
 
-    if (!directA) scrA.ensure(use32 ? ((size_t)M * K + 1) / 2 : (size_t)M * K);
-    if (!directB) scrB.ensure(use32 ? ((size_t)N * K + 1) / 2 : (size_t)N * K);
+    // K not a multiple of the GEMM's vector width (2 doubles / 4 floats): for large products
+    // both operands are gathered into rows of Kp >= K with zero padding so the 16-byte load
+    // path applies (the padding adds zero terms)
+    const long vw = use32 ? 4 : 2;
+    long Kp = K;
+    if (K % vw != 0 && flops > pad_min_flops && !aK.empty()) {
+      Kp = (K + vw - 1) / vw * vw;
+      directA = directB = false;
+    }
+    if (!directA) scrA.ensure(use32 ? ((size_t)M * Kp + 1) / 2 : (size_t)M * Kp);
+    if (!directB) scrB.ensure(use32 ? ((size_t)N * Kp + 1) / 2 : (size_t)N * Kp);
     const double* pA = a.p;
     const double* pB = b.p;
     if (!directA) {
-      gather(a, ordA, use32 ? nullptr : scrA.p, use32 ? reinterpret_cast<float*>(scrA.p) : nullptr);
+      gather(a, ordA, use32 ? nullptr : scrA.p, use32 ? reinterpret_cast<float*>(scrA.p) : nullptr, aK.size(), Kp);
       pA = scrA.p;
-      sAm = K;
+      sAm = Kp;
     }
     if (!directB) {
-      gather(b, ordB, use32 ? nullptr : scrB.p, use32 ? reinterpret_cast<float*>(scrB.p) : nullptr);
+      gather(b, ordB, use32 ? nullptr : scrB.p, use32 ? reinterpret_cast<float*>(scrB.p) : nullptr, bK.size(), Kp);
       pB = scrB.p;
-      sBn = K;
+      sBn = Kp;
     }
     GemmArgs g;
     g.M = (int)M;
     g.N = (int)N;
-    g.K = (int)K;
-    if (M > 2147483647L || N > 2147483647L || K > 2147483647L) throw Err(RIC_E_ARG, "contraction too large");
+    g.K = (int)Kp;
+    if (M > 2147483647L || N > 2147483647L || Kp > 2147483647L) throw Err(RIC_E_ARG, "contraction too large");
     g.lda = sAm;
     g.ldb = sBn;
     scrK.ensure(64L * 1024 * 1024);

@@ -52,6 +52,10 @@ CASES = [
     ("single reference nc4 nv9 naux20", S.custom_config("sr", 4, 0, 9, 20, 8)),
     ("no core CAS(2,2) nv7 naux15", S.custom_config("nocore", 0, 2, 7, 15, 9)),
     ("CAS(6,6) nc2 nv11 naux25", S.custom_config("cas66", 2, 6, 11, 25, 10)),
+    ("no virtuals nc3 CAS(3,3) naux10", S.custom_config("nov", 3, 3, 0, 10, 14)),
+    ("active space only CAS(4,4) naux9", S.custom_config("cas", 0, 4, 0, 9, 15)),
+    ("one of each nc1 na1 nv1 naux3", S.custom_config("one", 1, 1, 1, 3, 16)),
+    ("single active orbital nc2 na1 nv3 naux5", S.custom_config("na1", 2, 1, 3, 5, 17)),
 ]
 
 
@@ -155,3 +159,26 @@ def test_ladder_matches_sampled_definition(nc, na, nv, naux):
     g = np.array([got[i] for i in idx])
     assert np.abs(g - want).max() / max(1.0, np.abs(want).max()) < RTOL
     assert np.array_equal(got, got.transpose(1, 0, 3, 2))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32mix"])
+def test_residual_with_padded_operands(monkeypatch, precision):
+    """Every product with a K that is not a multiple of the load width gathered with zero padding
+    (the path large products take), odd extents throughout: still the oracle's residual."""
+    from paper_2511_03567_amd import ric
+    monkeypatch.setenv("RIC_PAD_MIN_FLOPS", "0")
+    monkeypatch.setenv("RIC_FP32_MIN_FLOPS", "0")   # mixed: every product with fp32 operands
+    cfg = S.custom_config("odd", 3, 4, 21, 29, 18)
+    inp = S.make_inputs(cfg)
+    ctx, t = _ctx(cfg, inp)
+    T1, T2 = _amps(cfg, 19)
+    nH, nP = cfg.nc + cfg.na, cfg.na + cfg.nv
+    R1 = torch.zeros((nH, nP), dtype=torch.float64, device="cuda")
+    R2 = torch.zeros((nH, nH, nP, nP), dtype=torch.float64, device="cuda")
+    prec = ric.RIC_FP64 if precision == "fp64" else ric.RIC_FP32MIX
+    ctx.residual(t(T1), t(T2), R1, R2, prec)
+    ref = R.Reference(cfg.nc, cfg.na, cfg.nv, inp.f, inp.B, inp.G1, inp.G2, inp.G3)
+    r1, r2 = ref.residual(T1, T2)
+    tol = RTOL if precision == "fp64" else 1e-5
+    assert _rel(R1.cpu().numpy(), r1) < tol
+    assert _rel(R2.cpu().numpy(), r2) < tol

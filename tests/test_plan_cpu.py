@@ -28,7 +28,8 @@ def plan_text():
 
 
 @pytest.mark.parametrize("nc,na,nv,naux,seed", [(2, 4, 10, 48, 1), (3, 4, 5, 12, 2), (0, 2, 7, 15, 3),
-                                                 (4, 0, 9, 20, 4), (1, 6, 4, 11, 5)])
+                                                 (4, 0, 9, 20, 4), (1, 6, 4, 11, 5), (3, 3, 0, 10, 6),
+                                                 (1, 1, 1, 3, 7)])
 def test_plan_matches_oracle(plan_text, nc, na, nv, naux, seed):
     cfg = S.custom_config("p", nc, na, nv, naux, seed)
     inp = S.make_inputs(cfg)
