@@ -164,8 +164,7 @@ def main():
                     help="also time one adjoint-residual evaluation J_r^T x")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this engine has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only: this engine has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
     os.environ.setdefault("RIC_PROGRESS", "1")
     import numpy as np
