@@ -150,6 +150,19 @@ int ric_flow_scale(ric_ctx* ctx, const double* L1, const double* L2, double s, d
 int ric_flow_fock_gradient(ric_ctx* ctx, const double* T1, const double* T2, const double* R1, const double* R2,
                            const double* L1, const double* L2, double s, double* dF);
 
+/* ---- vector operations for accelerated iterations (DIIS) ------------------------------
+ * The paper converges the amplitude equations with a DIIS-accelerated form of the iteration of
+ * eq. cc-update (Section 2.2); these two calls are
+ * the device work of that extrapolation: inner products of error vectors and linear
+ * combinations of amplitude vectors.  n elements, device pointers, enqueued on the context
+ * stream. */
+
+/* out (host) = sum_i a[i] b[i], summed in a fixed order (deterministic). */
+int ric_vec_dot(ric_ctx* ctx, const double* a, const double* b, long n, double* out);
+
+/* y <- alpha x + beta y (beta = 0 overwrites y without reading it). */
+int ric_vec_axpby(ric_ctx* ctx, double alpha, const double* x, double beta, double* y, long n);
+
 /* Milliseconds spent in the ladder during the last ric_residual/ric_ladder call,
  * measured with HIP events on the context stream (host output). */
 int ric_last_timings(const ric_ctx* ctx, double* ladder_ms, double* total_ms);

@@ -1535,6 +1535,33 @@ int ric_flow_fock_gradient(ric_ctx* ctx, const double* T1, const double* T2, con
   });
 }
 
+int ric_vec_dot(ric_ctx* ctx, const double* a, const double* b, long n, double* out) {
+  return guard(ctx, [&] {
+    if (!a || !b || !out || n < 0) throw Err(RIC_E_ARG, "bad vector arguments");
+    ctx->red.ensure(1024);
+    ctx->Edev.ensure(4);
+    HIPCHK(ric::fill(ctx->Edev.p, 1, 0.0, ctx->stream));
+    HIPCHK(ric::dot_accumulate(a, b, n, 1.0, ctx->Edev.p, ctx->red.p, ctx->stream));
+    double v = 0.0;
+    HIPCHK(hipMemcpyAsync(&v, ctx->Edev.p, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    *out = v;
+  });
+}
+
+int ric_vec_axpby(ric_ctx* ctx, double alpha, const double* x, double beta, double* y, long n) {
+  return guard(ctx, [&] {
+    if (!x || !y || n < 0) throw Err(RIC_E_ARG, "bad vector arguments");
+    Iter it;
+    it.nd = 1;
+    it.ext[0] = n;
+    it.so[0] = 1;
+    it.si[0] = 1;
+    it.total = n;
+    HIPCHK(ric::strided_copy(it, alpha, x, beta, y, ctx->stream));
+  });
+}
+
 int ric_last_timings(const ric_ctx* ctx, double* ladder_ms, double* total_ms) {
   if (!ctx) return RIC_E_ARG;
   if (ladder_ms) *ladder_ms = ctx->ladder_ms;

@@ -8,6 +8,7 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -59,12 +60,14 @@ def library():
     lib.ric_lambda_update.argtypes = [P] * 7 + [D, ctypes.POINTER(D)]
     lib.ric_flow_scale.argtypes = [P, P, P, D, P, P]
     lib.ric_flow_fock_gradient.argtypes = [P] * 7 + [D, P]
+    lib.ric_vec_dot.argtypes = [P, P, P, ctypes.c_long, ctypes.POINTER(D)]
+    lib.ric_vec_axpby.argtypes = [P, D, P, D, P, ctypes.c_long]
     lib.ric_last_error.argtypes = [P]
     lib.ric_last_error.restype = ctypes.c_char_p
     for fn in ("ric_create", "ric_set_spaces", "ric_load_fock", "ric_load_df", "ric_load_rdms",
                "ric_residual", "ric_update", "ric_energy", "ric_ladder", "ric_last_timings",
                "ric_adjoint_residual", "ric_energy_gradient", "ric_lambda_update", "ric_flow_scale",
-               "ric_flow_fock_gradient"):
+               "ric_flow_fock_gradient", "ric_vec_dot", "ric_vec_axpby"):
         getattr(lib, fn).restype = I
     _lib = lib
     return lib
@@ -199,6 +202,21 @@ class Context:
             self.h, _ptr(T1, s1, "T1"), _ptr(T2, s2, "T2"), _ptr(R1, s1, "R1"), _ptr(R2, s2, "R2"),
             _ptr(L1, s1, "L1"), _ptr(L2, s2, "L2"), float(s), _ptr(dF, (self.n, self.n), "dF")))
 
+    # --- vector operations (DIIS) --------------------------------------------------------
+    def dot(self, a, b):
+        if a.shape != b.shape:
+            raise ValueError("shape mismatch")
+        out = ctypes.c_double()
+        self._check(self.lib.ric_vec_dot(self.h, _ptr(a, a.shape, "a"), _ptr(b, b.shape, "b"), a.numel(),
+                                         ctypes.byref(out)))
+        return out.value
+
+    def axpby(self, alpha, x, beta, y):
+        if x.shape != y.shape:
+            raise ValueError("shape mismatch")
+        self._check(self.lib.ric_vec_axpby(self.h, float(alpha), _ptr(x, x.shape, "x"), float(beta),
+                                           _ptr(y, y.shape, "y"), y.numel()))
+
     def timings(self):
         a = ctypes.c_double()
         b = ctypes.c_double()
@@ -216,12 +234,63 @@ def masks(nc, na, nv, device):
     return m1, m2
 
 
+class _Diis:
+    """Pulay's direct inversion in the iterative subspace over amplitude pairs (T1, T2).
+
+    Keeps the last `size` updated amplitudes U_i and their steps e_i = U_i - T_i; the
+    extrapolation is sum c_i U_i with sum c_i = 1 minimizing |sum c_i e_i|.
+    """
+
+    def __init__(self, ctx: Context, size):
+        self.ctx = ctx
+        self.size = size
+        self.U = []
+        self.E = []
+        self.B = np.zeros((0, 0))
+
+    def reset(self):
+        self.U, self.E, self.B = [], [], np.zeros((0, 0))
+
+    def push(self, U, E):
+        if len(self.U) == self.size:
+            self.U.pop(0)
+            self.E.pop(0)
+            self.B = self.B[1:, 1:]
+        self.U.append(U)
+        self.E.append(E)
+        m = len(self.E)
+        row = [sum(self.ctx.dot(a, b) for a, b in zip(E, self.E[j])) for j in range(m)]
+        B = np.zeros((m, m))
+        B[:m - 1, :m - 1] = self.B
+        B[m - 1, :] = row
+        B[:, m - 1] = row
+        self.B = B
+
+    def extrapolate(self, T1, T2):
+        m = len(self.U)
+        if m < 2:
+            return False
+        A = np.zeros((m + 1, m + 1))
+        scale = max(np.abs(np.diag(self.B)).max(), 1e-300)
+        A[:m, :m] = self.B / scale
+        A[m, :m] = A[:m, m] = -1.0
+        rhs = np.zeros(m + 1)
+        rhs[m] = -1.0
+        c = np.linalg.lstsq(A, rhs, rcond=None)[0][:m]
+        for T, k in ((T1, 0), (T2, 1)):
+            for j in range(m):
+                self.ctx.axpby(c[j], self.U[j][k], 0.0 if j == 0 else 1.0, T)
+        return True
+
+
 def solve(ctx: Context, s, tol=1e-8, max_iter=200, precision=RIC_FP64, polish_tol=None, T1=None, T2=None,
-          log=None):
-    """Regularized Jacobi iteration from T = 0 until ||t_new - t||_2 < tol.
+          log=None, diis=0, diis_start=2):
+    """Regularized iteration (eq. ric-update) from T = 0 until ||t_new - t||_2 < tol.
 
     precision=RIC_FP32MIX: iterate with mixed-precision residuals until the step
     falls below polish_tol (default 1e-6) or stalls, then continue in fp64 to tol.
+    diis > 0: accelerate with DIIS over the last `diis` iterates from iteration diis_start on
+    (the history restarts when the precision switches).
     Returns (E_corr, E0, T1, T2, iterations).
     """
     s1, s2 = ctx.amplitude_shapes()
@@ -234,17 +303,28 @@ def solve(ctx: Context, s, tol=1e-8, max_iter=200, precision=RIC_FP64, polish_to
     mode = precision
     switch = polish_tol if polish_tol is not None else 1e-6
     prev = None
+    acc = _Diis(ctx, diis) if diis > 0 else None
     for it in range(1, max_iter + 1):
+        if acc is not None:
+            P1, P2 = T1.clone(), T2.clone()
         ctx.residual(T1, T2, R1, R2, mode)
         step = ctx.update(T1, T2, R1, R2, s) ** 0.5
         if log is not None:
             log.append({"iter": it, "step": step, "precision": "fp32mix" if mode == RIC_FP32MIX else "fp64"})
-        if mode == RIC_FP32MIX and (step < switch or (prev is not None and step > 0.9 * prev)):
+        if mode == RIC_FP32MIX and (step < switch or (prev is not None and step > 0.9 * prev and acc is None)):
             mode = RIC_FP64
+            if acc is not None:
+                acc.reset()
         elif mode == RIC_FP64 and step < tol:
             e, e0 = ctx.energy(T1, T2)
             return e, e0, T1, T2, it
         prev = step
+        if acc is not None:
+            ctx.axpby(-1.0, T1, 1.0, P1)      # P = T_old - U: the negated step
+            ctx.axpby(-1.0, T2, 1.0, P2)
+            acc.push((T1.clone(), T2.clone()), (P1, P2))
+            if it >= diis_start:
+                acc.extrapolate(T1, T2)
     raise RicError(RIC_E_NOCONV, f"regularized iteration did not converge in {max_iter} iterations")
 
 
