@@ -150,6 +150,14 @@ int ric_flow_scale(ric_ctx* ctx, const double* L1, const double* L2, double s, d
 int ric_flow_fock_gradient(ric_ctx* ctx, const double* T1, const double* T2, const double* R1, const double* R2,
                            const double* L1, const double* L2, double s, double* dF);
 
+/* Generalized Fock matrix of the reference (Section 2.1) from the one-electron Hamiltonian:
+ * f[p][q] = h[p][q] + sum_rs (pq|rs) D[r][s] - sum_{k in core} (pk|kq)
+ *           - 1/2 sum_{t,u in active} Gamma1[t][u] (pu|tq),
+ * with D the spin-summed reference 1-RDM (2 on the core diagonal, Gamma1 on the active
+ * block) and (pq|rs) from the loaded DF factors.  h, f: n x n row-major device pointers;
+ * f is overwritten and not loaded into the context (pass it to ric_load_fock). */
+int ric_build_fock(ric_ctx* ctx, const double* h, double* f);
+
 /* ---- vector operations for accelerated iterations (DIIS) ------------------------------
  * The paper converges the amplitude equations with a DIIS-accelerated form of the iteration of
  * eq. cc-update (Section 2.2); these two calls are

@@ -22,6 +22,10 @@ hipError_t strided_copy_f32f32(const Iter& it, const float* in, float* out, hipS
 hipError_t fill(double* p, long n, double v, hipStream_t st);
 hipError_t symmetrize_pairs(double* x, int nh, int np, hipStream_t st);
 hipError_t mask_active(double* r1, double* r2, int nc, int na, int nv, hipStream_t st);
+// w = spin-summed reference 1-RDM over all orbitals (2 on the core diagonal, Gamma1 on the active block)
+hipError_t fock_weights(double* w, int n, int nc, int na, const double* g1, hipStream_t st);
+// out[i] += alpha * sum_X B[X][i] d[X], B row-major [nx][n2]
+hipError_t column_dot(const double* B, const double* d, int nx, long n2, double alpha, double* out, hipStream_t st);
 // x <- scale (x + x^T(pairs)) over [nh][nh][np][np]
 hipError_t symmetrize_pairs_scaled(double* x, int nh, int np, double scale, hipStream_t st);
 // Lagrangian iteration L <- g + Delta phi(Delta) L + j (stored amplitudes); norm2[0] = ||L_new - L||^2

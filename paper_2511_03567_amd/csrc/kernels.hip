@@ -295,6 +295,31 @@ flow_fock_kernel(const double* __restrict__ t1, const double* __restrict__ t2, c
   if (threadIdx.x == 0) df[(long)p * n + p] += acc;
 }
 
+// ---- generalized Fock matrix from h (Section 2.1) --------------------------------------------
+
+// w[p,q] = 2 delta_pq on core orbitals, Gamma1[t,u] on the active block, 0 elsewhere: the
+// spin-summed 1-RDM of the reference
+__global__ void fock_weights_kernel(double* __restrict__ w, int n, int nc, int na, const double* __restrict__ g1) {
+  const long total = (long)n * n;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
+    const int p = (int)(t / n), q = (int)(t % n);
+    double v = 0.0;
+    if (p < nc && q < nc) v = p == q ? 2.0 : 0.0;
+    else if (p >= nc && p < nc + na && q >= nc && q < nc + na) v = g1[(p - nc) * na + (q - nc)];
+    w[t] = v;
+  }
+}
+
+// out[i] += alpha * sum_X B[X][i] d[X] over the n2 columns i of B (row-major [nx][n2])
+__global__ void column_dot_kernel(const double* __restrict__ B, const double* __restrict__ d, int nx, long n2,
+                                  double alpha, double* __restrict__ out) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n2; i += (long)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int x = 0; x < nx; ++x) s += B[(long)x * n2 + i] * d[x];
+    out[i] += alpha * s;
+  }
+}
+
 __global__ void diag_kernel(const double* __restrict__ f, int n, double* __restrict__ eps) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) eps[i] = f[(long)i * n + i];
 }
@@ -630,6 +655,17 @@ hipError_t flow_fock_gradient(const double* t1, const double* t2, const double* 
   const int n = nc + na + nv;
   hipLaunchKernelGGL(flow_fock_kernel, dim3(n), dim3(kThreads), 0, st, t1, t2, r1, r2, l1, l2, eps, nc, na, nv, s,
                      df);
+  return hipGetLastError();
+}
+
+hipError_t fock_weights(double* w, int n, int nc, int na, const double* g1, hipStream_t st) {
+  const long total = (long)n * n;
+  hipLaunchKernelGGL(fock_weights_kernel, dim3(blocks_for(total)), dim3(kThreads), 0, st, w, n, nc, na, g1);
+  return hipGetLastError();
+}
+
+hipError_t column_dot(const double* B, const double* d, int nx, long n2, double alpha, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(column_dot_kernel, dim3(blocks_for(n2)), dim3(kThreads), 0, st, B, d, nx, n2, alpha, out);
   return hipGetLastError();
 }
 

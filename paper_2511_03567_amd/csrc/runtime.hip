@@ -1535,6 +1535,77 @@ int ric_flow_fock_gradient(ric_ctx* ctx, const double* T1, const double* T2, con
   });
 }
 
+int ric_build_fock(ric_ctx* ctx, const double* h, double* f) {
+  return guard(ctx, [&] {
+    if (!ctx->spaces || !ctx->have_B) throw Err(RIC_E_STATE, "DF factors must be loaded");
+    if (ctx->sz.na > 0 && !ctx->have_rdm) throw Err(RIC_E_STATE, "RDMs must be loaded when na > 0");
+    if (!h || !f) throw Err(RIC_E_ARG, "null pointer");
+    const int n = (int)ctx->sz.ext(RG), nc = ctx->sz.nc, na = ctx->sz.na, nx = ctx->sz.naux;
+    const long n2 = (long)n * n;
+    hipStream_t st = ctx->stream;
+    // f = h + sum_X B[X] (B[X] . D) - sum_i B_pi B_iq - 1/2 sum_tu Gamma_tu B_pu B_tq
+    HIPCHK(hipMemcpyAsync(f, h, n2 * sizeof(double), hipMemcpyDeviceToDevice, st));
+    ctx->scrA.ensure((size_t)n2);
+    ctx->scrB.ensure((size_t)nx);
+    HIPCHK(ric::fock_weights(ctx->scrA.p, n, nc, na, na ? ctx->g1.p : nullptr, st));
+    GemmArgs gd;  // d[X] = sum_pq B[X,p,q] D[p,q]
+    gd.M = nx;
+    gd.N = 1;
+    gd.K = (int)n2;
+    gd.lda = n2;
+    gd.ldb = n2;
+    gd.C = ctx->scrB.p;
+    gd.ldc = 1;
+    ctx->scrK.ensure(64L * 1024 * 1024);
+    HIPCHK(ric::gemm_nt_f64(gd, ctx->B.p, ctx->scrA.p, st, ctx->scrK.p, ctx->scrK.n));
+    HIPCHK(ric::column_dot(ctx->B.p, ctx->scrB.p, nx, n2, 1.0, f, st));
+    // exchange with the core and active orbitals: Y[p][(X,k)] = B[X,p,k] over k in C + A, with
+    // the active columns contracted with Gamma1 / 2, then f -= Y Z^T (Z the same gather unweighted)
+    const int m = nc + na;
+    if (m > 0) {
+      ctx->scrC.ensure((size_t)n * nx * m);
+      ctx->scrC2.ensure((size_t)n * nx * m);
+      Iter it;  // scrC[p][X][k] = B[X][p][k]
+      it.nd = 3;
+      const long ex[3] = {n, nx, m}, so[3] = {(long)nx * m, m, 1}, si[3] = {n, n2, 1};
+      it.total = (long)n * nx * m;
+      for (int i = 0; i < 3; ++i) {
+        it.ext[i] = ex[i];
+        it.so[i] = so[i];
+        it.si[i] = si[i];
+      }
+      HIPCHK(ric::strided_copy(it, 1.0, ctx->B.p, 0.0, ctx->scrC.p, st));
+      // weighted copy: core columns as is, active columns Gamma1/2-contracted
+      HIPCHK(hipMemcpyAsync(ctx->scrC2.p, ctx->scrC.p, (size_t)n * nx * m * sizeof(double), hipMemcpyDeviceToDevice,
+                            st));
+      if (na > 0) {
+        GemmArgs ga;  // W[(p,X)][t] = 1/2 sum_u B[X,p,u] Gamma1[t,u]
+        ga.M = n * nx;
+        ga.N = na;
+        ga.K = na;
+        ga.alpha = 0.5;
+        ga.lda = m;
+        ga.ldb = na;
+        ga.C = ctx->scrC2.p + nc;
+        ga.ldc = m;
+        HIPCHK(ric::gemm_nt_f64(ga, ctx->scrC.p + nc, ctx->g1.p, st, ctx->scrK.p, ctx->scrK.n));
+      }
+      GemmArgs gk;  // f[p][q] -= sum_(X,k) Y[p][(X,k)] Z[q][(X,k)]
+      gk.M = n;
+      gk.N = n;
+      gk.K = nx * m;
+      gk.alpha = -1.0;
+      gk.beta = 1.0;
+      gk.lda = (long)nx * m;
+      gk.ldb = (long)nx * m;
+      gk.C = f;
+      gk.ldc = n;
+      HIPCHK(ric::gemm_nt_f64(gk, ctx->scrC2.p, ctx->scrC.p, st, ctx->scrK.p, ctx->scrK.n));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+  });
+}
+
 int ric_vec_dot(ric_ctx* ctx, const double* a, const double* b, long n, double* out) {
   return guard(ctx, [&] {
     if (!a || !b || !out || n < 0) throw Err(RIC_E_ARG, "bad vector arguments");

@@ -60,6 +60,7 @@ def library():
     lib.ric_lambda_update.argtypes = [P] * 7 + [D, ctypes.POINTER(D)]
     lib.ric_flow_scale.argtypes = [P, P, P, D, P, P]
     lib.ric_flow_fock_gradient.argtypes = [P] * 7 + [D, P]
+    lib.ric_build_fock.argtypes = [P, P, P]
     lib.ric_vec_dot.argtypes = [P, P, P, ctypes.c_long, ctypes.POINTER(D)]
     lib.ric_vec_axpby.argtypes = [P, D, P, D, P, ctypes.c_long]
     lib.ric_last_error.argtypes = [P]
@@ -67,7 +68,7 @@ def library():
     for fn in ("ric_create", "ric_set_spaces", "ric_load_fock", "ric_load_df", "ric_load_rdms",
                "ric_residual", "ric_update", "ric_energy", "ric_ladder", "ric_last_timings",
                "ric_adjoint_residual", "ric_energy_gradient", "ric_lambda_update", "ric_flow_scale",
-               "ric_flow_fock_gradient", "ric_vec_dot", "ric_vec_axpby"):
+               "ric_flow_fock_gradient", "ric_vec_dot", "ric_vec_axpby", "ric_build_fock"):
         getattr(lib, fn).restype = I
     _lib = lib
     return lib
@@ -202,6 +203,10 @@ class Context:
             self.h, _ptr(T1, s1, "T1"), _ptr(T2, s2, "T2"), _ptr(R1, s1, "R1"), _ptr(R2, s2, "R2"),
             _ptr(L1, s1, "L1"), _ptr(L2, s2, "L2"), float(s), _ptr(dF, (self.n, self.n), "dF")))
 
+    def build_fock(self, h, f):
+        """Generalized Fock matrix f from h with the loaded DF factors and RDMs (not loaded)."""
+        self._check(self.lib.ric_build_fock(self.h, _ptr(h, (self.n, self.n), "h"), _ptr(f, (self.n, self.n), "f")))
+
     # --- vector operations (DIIS) --------------------------------------------------------
     def dot(self, a, b):
         if a.shape != b.shape:
@@ -328,11 +333,12 @@ def solve(ctx: Context, s, tol=1e-8, max_iter=200, precision=RIC_FP64, polish_to
     raise RicError(RIC_E_NOCONV, f"regularized iteration did not converge in {max_iter} iterations")
 
 
-def solve_lambda(ctx: Context, T1, T2, s, tol=1e-10, max_iter=400, log=None):
+def solve_lambda(ctx: Context, T1, T2, s, tol=1e-10, max_iter=400, log=None, diis=0):
     """Lagrange multipliers of the converged regularized iteration.
 
     Iterates L <- dE/dT + Delta phi L + J_r^T(phi L) from L = dE/dT until the step norm
-    falls below tol.  Returns (L1, L2, dE/df at fixed T, dE/dB at fixed T, iterations).
+    falls below tol (with DIIS over the last `diis` iterates when diis > 0).
+    Returns (L1, L2, dE/df at fixed T, dE/dB at fixed T, iterations).
     """
     s1, s2 = ctx.amplitude_shapes()
     n, nx = ctx.n, ctx.sizes[3]
@@ -342,7 +348,10 @@ def solve_lambda(ctx: Context, T1, T2, s, tol=1e-10, max_iter=400, log=None):
     ctx.energy_gradient(T1, T2, G1, G2, eF, eB)
     L1, L2 = G1.clone(), G2.clone()
     P1, P2, J1, J2 = z(s1), z(s2), z(s1), z(s2)
+    acc = _Diis(ctx, diis) if diis > 0 else None
     for it in range(1, max_iter + 1):
+        if acc is not None:
+            O1, O2 = L1.clone(), L2.clone()
         ctx.flow_scale(L1, L2, s, P1, P2)
         ctx.adjoint_residual(T1, T2, P1, P2, J1, J2)
         step = ctx.lambda_update(L1, L2, G1, G2, J1, J2, s) ** 0.5
@@ -350,12 +359,18 @@ def solve_lambda(ctx: Context, T1, T2, s, tol=1e-10, max_iter=400, log=None):
             log.append({"iter": it, "step": step})
         if step < tol:
             return L1, L2, eF, eB, it
+        if acc is not None:
+            ctx.axpby(-1.0, L1, 1.0, O1)
+            ctx.axpby(-1.0, L2, 1.0, O2)
+            acc.push((L1.clone(), L2.clone()), (O1, O2))
+            if it >= 2:
+                acc.extrapolate(L1, L2)
     raise RicError(RIC_E_NOCONV, f"Lagrangian iteration did not converge in {max_iter} iterations")
 
 
-def energy_gradient(ctx: Context, T1, T2, s, tol=1e-10, max_iter=400):
+def energy_gradient(ctx: Context, T1, T2, s, tol=1e-10, max_iter=400, diis=0):
     """dE_corr/df and dE_corr/dB at the converged amplitudes T1, T2 (flow parameter s)."""
-    L1, L2, dF, dB, _ = solve_lambda(ctx, T1, T2, s, tol, max_iter)
+    L1, L2, dF, dB, _ = solve_lambda(ctx, T1, T2, s, tol, max_iter, diis=diis)
     s1, s2 = ctx.amplitude_shapes()
     dev = T1.device
     P1 = torch.zeros(s1, dtype=torch.float64, device=dev)

@@ -166,3 +166,18 @@ def test_chunked_accumulators_match_whole(monkeypatch):
         ctx.close()
     for a, b in zip(outs[0], outs[1]):
         assert np.abs(a - b).max() <= 1e-12 * max(1.0, np.abs(a).max())
+
+
+def test_lambda_diis_matches_plain_iteration():
+    """The Lagrange multipliers with DIIS equal those of the plain iteration, in fewer steps."""
+    from paper_2511_03567_amd import ric
+    cfg = S.CONFIGS["tiny_cas44"]
+    inp = S.make_inputs(cfg)
+    ctx, t = _ctx(cfg, inp.f, inp.B, inp)
+    _, _, T1, T2, _ = ric.solve(ctx, cfg.s, tol=1e-12, diis=6)
+    L1a, L2a, _, _, ita = ric.solve_lambda(ctx, T1, T2, cfg.s, tol=1e-12)
+    L1b, L2b, _, _, itb = ric.solve_lambda(ctx, T1, T2, cfg.s, tol=1e-12, diis=6)
+    print(f"  Lagrangian iterations: plain {ita}, DIIS {itb}", flush=True)
+    assert itb < ita
+    for a, b in ((L1a, L1b), (L2a, L2b)):
+        assert (a - b).abs().max().item() <= 1e-9 * max(1.0, a.abs().max().item())

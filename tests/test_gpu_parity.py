@@ -182,3 +182,15 @@ def test_residual_with_padded_operands(monkeypatch, precision):
     tol = RTOL if precision == "fp64" else 1e-5
     assert _rel(R1.cpu().numpy(), r1) < tol
     assert _rel(R2.cpu().numpy(), r2) < tol
+
+
+@pytest.mark.parametrize("name,cfg", [CASES[0], CASES[1], CASES[2], CASES[3]], ids=[c[0] for c in CASES[:4]])
+def test_fock_from_core_hamiltonian(name, cfg):
+    """f(h) on the GPU inverts the oracle's h(f) (generalized Fock matrix, Section 2.1)."""
+    inp = S.make_inputs(cfg)
+    ctx, t = _ctx(cfg, inp)
+    ref = R.Reference(cfg.nc, cfg.na, cfg.nv, inp.f, inp.B, inp.G1, inp.G2, inp.G3)
+    h = ref.core_hamiltonian()
+    f = torch.zeros((cfg.n, cfg.n), dtype=torch.float64, device="cuda")
+    ctx.build_fock(t(h), f)
+    assert _rel(f.cpu().numpy(), inp.f) < 1e-12
