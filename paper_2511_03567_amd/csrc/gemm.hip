@@ -302,12 +302,30 @@ hipError_t launch_geo(const GemmArgs& g, const T* A, const T* B, TC* C, hipStrea
                       size_t scratch_elems) {
   constexpr int BM = Gm::BM, BN = Gm::BN;
   const int tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
+  // Split K when there are few tiles, choosing the factor so the workgroups fill whole rounds
+  // of the resident slots (256 CUs x 2 workgroups of these geometries): the smallest factor
+  // reaching 95 % of the slots in every round, else the best one found.
   int ksplit = 1;
-  if (g.K > 0) {
-    const long blocks = (long)tiles * g.batch;
-    while (blocks * ksplit < 1024 && (long)g.K / (ksplit * 2) >= 512) ksplit *= 2;
-    while (ksplit > 1 && (size_t)ksplit * g.batch * g.M * g.N > scratch_elems) ksplit /= 2;
-    if (sizeof(TC) != sizeof(double)) ksplit = 1;
+  if (g.K > 0 && sizeof(TC) == sizeof(double)) {
+    constexpr long kSlots = 512;
+    const long base = (long)tiles * g.batch;
+    auto fill = [&](long ks) {
+      const long w = base * ks;
+      return (double)w / (double)(((w + kSlots - 1) / kSlots) * kSlots);
+    };
+    if (base < 4 * kSlots) {
+      double best = fill(1);
+      for (int ks = 2; ks <= 64; ++ks) {
+        if ((long)g.K / ks < 512) break;
+        if ((size_t)ks * g.batch * g.M * g.N > scratch_elems) break;
+        const double e = fill(ks);
+        if (e > best + 0.01) {
+          best = e;
+          ksplit = ks;
+        }
+        if (best >= 0.95) break;
+      }
+    }
   }
   while (ksplit > 1 && (long)g.batch * ksplit > 65535) ksplit /= 2;
   if ((long)g.batch * ksplit > 65535) return hipErrorInvalidValue;

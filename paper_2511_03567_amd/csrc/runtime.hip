@@ -207,6 +207,9 @@ struct Pool {
 
 }  // namespace
 
+// fp64 elements of split-K partial tiles (2 GiB)
+constexpr size_t kSplitScratch = 256UL * 1024 * 1024;
+
 struct ric_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -595,7 +598,7 @@ struct ric_ctx {
     if (M > 2147483647L || N > 2147483647L || Kp > 2147483647L) throw Err(RIC_E_ARG, "contraction too large");
     g.lda = sAm;
     g.ldb = sBn;
-    scrK.ensure(64L * 1024 * 1024);
+    scrK.ensure(kSplitScratch);
     if (directC) {
       g.alpha = alpha;
       g.beta = fresh ? 0.0 : 1.0;
@@ -747,7 +750,7 @@ struct ric_ctx {
       g.ldb = nx;
       g.C = wbuf.p;
       g.ldc = nq * ns;
-      scrK.ensure(64L * 1024 * 1024);
+      scrK.ensure(kSplitScratch);
       HIPCHK(ric::gemm_nt_f64(g, dfa.p, l2buf.p, stream, scrK.p, scrK.n));
       View e;
       e.p = wbuf.p;
@@ -812,7 +815,7 @@ struct ric_ctx {
     wbuf2.ensure(mixed ? (wel + 1) / 2 : wel);
     scrC.ensure((size_t)nhp * chunk * np_);
     scrC2.ensure((size_t)std::max<long>(1, nhm) * chunk * np_);
-    scrK.ensure(64L * 1024 * 1024);
+    scrK.ensure(kSplitScratch);
     for (int c0 = 0; c0 < np_; c0 += (int)chunk) {
       const int c1 = std::min<int>(np_, c0 + (int)chunk);
       const int rows = c1 - c0;
@@ -907,7 +910,7 @@ struct ric_ctx {
     wbuf.ensure((size_t)chunk * np_ * pp);
     wbuf2.ensure((size_t)chunk * np_ * pp);
     scrC.ensure((size_t)chunk * np_ * nx);
-    scrK.ensure(64L * 1024 * 1024);
+    scrK.ensure(kSplitScratch);
     for (long c0 = 0; c0 < np_; c0 += chunk) {
       const long rows = std::min(chunk, np_ - c0);
       GemmArgs g1;  // V1[(c,d)][(e,f)]
@@ -1556,7 +1559,7 @@ int ric_build_fock(ric_ctx* ctx, const double* h, double* f) {
     gd.ldb = n2;
     gd.C = ctx->scrB.p;
     gd.ldc = 1;
-    ctx->scrK.ensure(64L * 1024 * 1024);
+    ctx->scrK.ensure(kSplitScratch);
     HIPCHK(ric::gemm_nt_f64(gd, ctx->B.p, ctx->scrA.p, st, ctx->scrK.p, ctx->scrK.n));
     HIPCHK(ric::column_dot(ctx->B.p, ctx->scrB.p, nx, n2, 1.0, f, st));
     // exchange with the core and active orbitals: Y[p][(X,k)] = B[X,p,k] over k in C + A, with
