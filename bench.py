@@ -25,7 +25,7 @@ METRIC = "s/residual-iteration & TFLOP/s, 809-orb CAS(12,12); FP32-mixed vs FP64
 # HBM bytes of one ladder call at the 809-orbital shape, from the FETCH_SIZE / WRITE_SIZE passes in
 # profiles/ladder_b12_cas1212_hbm_counters.md (scaled by the copy-kernel calibration).  Valid only
 # for the kernel sources they were taken on; any change to them reports null.
-LADDER_TRAFFIC = {"bytes": 8.876e13, "sources_sha256": "8cade218cf65e146", "workload": "b12_cas1212"}
+LADDER_TRAFFIC = {"bytes": 8.867e13, "sources_sha256": "4c228bf959e7c17e", "workload": "b12_cas1212"}
 
 
 def log(msg):
@@ -142,12 +142,18 @@ def cpu_baseline(flops_full, plan_path):
     el = time.perf_counter() - t0
     f_sample, _ = plan_flops(nc, na, nv, nx, plan_path)
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), "")
+    except OSError:
+        pass
     return {
         "value": el * flops_full / f_sample,
         "unit": "s/residual-iteration",
         "cores": min(threads, os.cpu_count() or 1),
         "kind": "oracle",
-        "sample": (f"oracle residual + update at nc={nc} na={na} nv={nv} naux={nx} took {el:.2f} s; "
+        "sample": (f"oracle residual + update at nc={nc} na={na} nv={nv} naux={nx} took {el:.2f} s on {model}; "
                    f"scaled by algorithmic flops {flops_full:.3e}/{f_sample:.3e} (extrapolated)"),
     }
 
@@ -212,9 +218,18 @@ def main():
     del ca, cb
     log("calibration copy done (1 GiB read, 1 GiB written)")
 
+    upd_ms = []
+
     def step(prec):
         ctx.residual(T1, T2, R1, R2, prec)
-        return ctx.update(T1, T2, R1, R2, cfg.s)
+        ea = torch.cuda.Event(enable_timing=True)
+        eb = torch.cuda.Event(enable_timing=True)
+        ea.record()          # the library works on torch's current stream
+        n2 = ctx.update(T1, T2, R1, R2, cfg.s)
+        eb.record()
+        eb.synchronize()
+        upd_ms.append(ea.elapsed_time(eb))
+        return n2
 
     for w in range(args.warmup):
         step(ric.RIC_FP64)
@@ -262,6 +277,11 @@ def main():
                      "ladder_algorithmic_flops": lflops},
         "nonladder_tflops": (flops - lflops) / (dt - ladder_s) / 1e12 if dt > ladder_s else None,
     }
+    # regularized update: reads T and R, writes T (24 B per stored amplitude), HBM-bound
+    n_amp = T1.numel() + T2.numel()
+    u_s = min(upd_ms[-args.steps:]) / 1e3
+    out["update"] = {"bound": "hbm", "s": u_s, "achieved": 24.0 * n_amp / u_s / 1e9, "peak": 8000.0,
+                     "unit": "GB/s", "frac": 24.0 * n_amp / u_s / 1e9 / 8000.0}
     if not args.no_mixed:
         # FP32-mixed residual at the starting amplitudes, against the FP64 one there
         if args.steps + args.warmup != 1:

@@ -39,10 +39,10 @@ hipError_t flow_scale(const double* l1, const double* l2, const double* eps, int
 hipError_t flow_fock_gradient(const double* t1, const double* t2, const double* r1, const double* r2,
                               const double* l1, const double* l2, const double* eps, int nc, int na, int nv,
                               double s, double* df, hipStream_t st);
-// out[0] += alpha * sum a[i] b[i] (deterministic two-pass); partial needs 1024 doubles
+// out[0] += alpha * sum a[i] b[i] (deterministic two-pass); partial needs 4096 doubles
 hipError_t dot_accumulate(const double* a, const double* b, long n, double alpha, double* out, double* partial,
                           hipStream_t st);
-// regularized update of T1, T2 in place; norm2[0] = ||t_new - t||^2; partial needs 1024 doubles
+// regularized update of T1, T2 in place; norm2[0] = ||t_new - t||^2; partial needs 4096 doubles
 hipError_t ric_update_kernel(double* t1, double* t2, const double* r1, const double* r2, const double* eps, int nc,
                              int na, int nv, double s, double* partial, double* norm2, hipStream_t st);
 hipError_t fock_diagonal(const double* f, int n, double* eps, hipStream_t st);

@@ -15,7 +15,7 @@ namespace ric {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kRedBlocks = 1024;
+constexpr int kRedBlocks = 4096;  // partial sums of the two-pass reductions (callers hold that many doubles)
 
 inline int blocks_for(long n, int per = kThreads) {
   long b = (n + per - 1) / per;
@@ -129,6 +129,24 @@ __global__ void finish_sum(const double* __restrict__ partial, int n, double alp
 
 // ---- regularized update -------------------------------------------------------------------
 
+// (k, l, c, d) of element u of a [nh][nh][np][np] array; 32-bit divisions below 2^32 elements
+__device__ inline void amp2_index(long u, int nh, int np, int& k, int& l, int& c, int& d) {
+  if (u < 4294967296L) {
+    unsigned v = (unsigned)u;
+    d = (int)(v % (unsigned)np);
+    v /= (unsigned)np;
+    c = (int)(v % (unsigned)np);
+    v /= (unsigned)np;
+    l = (int)(v % (unsigned)nh);
+    k = (int)(v / (unsigned)nh);
+  } else {
+    d = (int)(u % np);
+    c = (int)((u / np) % np);
+    l = (int)((u / ((long)np * np)) % nh);
+    k = (int)(u / ((long)np * np * nh));
+  }
+}
+
 __device__ inline double phi(double D, double s) {
   // (1 - exp(-s D^2)) / D with the limit 0 at D = 0
   if (D == 0.0) return 0.0;
@@ -158,10 +176,8 @@ update_kernel(double* __restrict__ t1, double* __restrict__ t2, const double* __
       t1[t] = nw;
     } else {
       const long u = t - n1;
-      const int d = (int)(u % np);
-      const int c = (int)((u / np) % np);
-      const int l = (int)((u / ((long)np * np)) % nh);
-      const int k = (int)(u / ((long)np * np * nh));
+      int k, l, c, d;
+      amp2_index(u, nh, np, k, l, c, d);
       if (k >= nc && l >= nc && c < na && d < na) continue;
       const double D = eps[k] + eps[l] - eps[nc + c] - eps[nc + d];
       const double nw = (t2[u] * D + r2[u]) * phi(D, s);
@@ -208,10 +224,8 @@ lambda_kernel(double* __restrict__ l1, double* __restrict__ l2, const double* __
       j = j1[t];
     } else {
       const long u = t - n1;
-      const int d = (int)(u % np);
-      const int c = (int)((u / np) % np);
-      const int ll = (int)((u / ((long)np * np)) % nh);
-      const int k = (int)(u / ((long)np * np * nh));
+      int k, ll, c, d;
+      amp2_index(u, nh, np, k, ll, c, d);
       masked = k >= nc && ll >= nc && c < na && d < na;
       D = eps[k] + eps[ll] - eps[nc + c] - eps[nc + d];
       l = l2 + u;
@@ -241,10 +255,8 @@ __global__ void flow_scale_kernel(const double* __restrict__ l1, const double* _
       o1[t] = (k >= nc && c < na) ? 0.0 : phi(D, s) * l1[t];
     } else {
       const long u = t - n1;
-      const int d = (int)(u % np);
-      const int c = (int)((u / np) % np);
-      const int ll = (int)((u / ((long)np * np)) % nh);
-      const int k = (int)(u / ((long)np * np * nh));
+      int k, ll, c, d;
+      amp2_index(u, nh, np, k, ll, c, d);
       const double D = eps[k] + eps[ll] - eps[nc + c] - eps[nc + d];
       o2[u] = (k >= nc && ll >= nc && c < na && d < na) ? 0.0 : phi(D, s) * l2[u];
     }

@@ -545,7 +545,7 @@ struct ric_ctx {
       scrB.ensure(cb ? 0 : K);
       if (ca) pa = a.p; else { gather(a, ka, scrA.p, nullptr); pa = scrA.p; }
       if (cb) pb = b.p; else { gather(b, kb, scrB.p, nullptr); pb = scrB.p; }
-      red.ensure(1024);
+      red.ensure(4096);
       if (fresh) HIPCHK(ric::fill(out.p, 1, 0.0, stream));
       HIPCHK(ric::dot_accumulate(pa, pb, K, alpha, out.p, red.p, stream));
       return;
@@ -1393,7 +1393,7 @@ int ric_update(ric_ctx* ctx, double* T1, double* T2, const double* R1, const dou
     ctx->require_loaded();
     if (!T1 || !T2 || !R1 || !R2) throw Err(RIC_E_ARG, "null amplitude/residual pointer");
     if (!(s >= 0.0)) throw Err(RIC_E_ARG, "flow parameter must be >= 0");
-    ctx->red.ensure(1024);
+    ctx->red.ensure(4096);
     ctx->Edev.ensure(4);
     HIPCHK(ric::ric_update_kernel(T1, T2, R1, R2, ctx->eps.p, ctx->sz.nc, ctx->sz.na, ctx->sz.nv, s, ctx->red.p,
                                   ctx->Edev.p + 1, ctx->stream));
@@ -1504,7 +1504,7 @@ int ric_lambda_update(ric_ctx* ctx, double* L1, double* L2, const double* G1, co
     ctx->require_loaded();
     if (!L1 || !L2 || !G1 || !G2 || !J1 || !J2) throw Err(RIC_E_ARG, "null pointer");
     if (!(s >= 0.0)) throw Err(RIC_E_ARG, "flow parameter must be >= 0");
-    ctx->red.ensure(1024);
+    ctx->red.ensure(4096);
     ctx->Edev.ensure(4);
     HIPCHK(ric::lambda_update(L1, L2, G1, G2, J1, J2, ctx->eps.p, ctx->sz.nc, ctx->sz.na, ctx->sz.nv, s, ctx->red.p,
                               ctx->Edev.p + 3, ctx->stream));
@@ -1612,7 +1612,7 @@ int ric_build_fock(ric_ctx* ctx, const double* h, double* f) {
 int ric_vec_dot(ric_ctx* ctx, const double* a, const double* b, long n, double* out) {
   return guard(ctx, [&] {
     if (!a || !b || !out || n < 0) throw Err(RIC_E_ARG, "bad vector arguments");
-    ctx->red.ensure(1024);
+    ctx->red.ensure(4096);
     ctx->Edev.ensure(4);
     HIPCHK(ric::fill(ctx->Edev.p, 1, 0.0, ctx->stream));
     HIPCHK(ric::dot_accumulate(a, b, n, 1.0, ctx->Edev.p, ctx->red.p, ctx->stream));
