@@ -877,7 +877,6 @@ struct ric_ctx {
     const long pp = np_ * np_, hh = nh * nh;
     lgx.ensure((size_t)pp * hh);
     lgt.ensure((size_t)pp * hh);
-    lgb.ensure((size_t)nx * pp);
     // [k][l][c][d] -> [(c,d)][(k,l)]
     auto pair_major = [&](const double* in, double* out) {
       Iter it;
@@ -893,10 +892,14 @@ struct ric_ctx {
     };
     pair_major(x, lgx.p);
     pair_major(taus, lgt.p);
+    // rows over (d,f) padded to an even length (zero tail) so the second product loads 16 bytes
+    const long ppad = (pp + 1) / 2 * 2;
+    lgb.ensure((size_t)nx * ppad);
+    if (ppad != pp) HIPCHK(ric::fill(lgb.p, nx * ppad, 0.0, stream));
     {  // B[X][P][P] contiguous over (d,f)
       Iter it;
       it.nd = 3;
-      const long ex[3] = {nx, np_, np_}, so[3] = {pp, np_, 1}, si[3] = {n * n, n, 1};
+      const long ex[3] = {nx, np_, np_}, so[3] = {ppad, np_, 1}, si[3] = {n * n, n, 1};
       it.total = nx * pp;
       for (int i = 0; i < 3; ++i) {
         it.ext[i] = ex[i];
@@ -905,12 +908,13 @@ struct ric_ctx {
       }
       HIPCHK(ric::strided_copy(it, 1.0, B.p + nc * n + nc, 0.0, lgb.p, stream));
     }
-    long chunk = std::max<long>(1, (long)(1.4e9 / ((double)np_ * pp)));
+    long chunk = std::max<long>(1, (long)(1.4e9 / ((double)np_ * ppad)));
     chunk = std::min(chunk, np_);
-    wbuf.ensure((size_t)chunk * np_ * pp);
+    wbuf.ensure((size_t)chunk * np_ * ppad);
     wbuf2.ensure((size_t)chunk * np_ * pp);
     scrC.ensure((size_t)chunk * np_ * nx);
     scrK.ensure(kSplitScratch);
+    if (ppad != pp) HIPCHK(ric::fill(wbuf.p, chunk * np_ * ppad, 0.0, stream));  // pad columns stay zero
     for (long c0 = 0; c0 < np_; c0 += chunk) {
       const long rows = std::min(chunk, np_ - c0);
       GemmArgs g1;  // V1[(c,d)][(e,f)]
@@ -922,10 +926,10 @@ struct ric_ctx {
       g1.C = wbuf2.p;
       g1.ldc = pp;
       HIPCHK(ric::gemm_nt_f64(g1, lgx.p + c0 * np_ * hh, lgt.p, stream, scrK.p, scrK.n));
-      {  // V2[(c,e)][(d,f)] <- V1[(c,d)][(e,f)]
+      {  // V2[(c,e)][(d,f)] <- V1[(c,d)][(e,f)], rows of length ppad
         Iter it;
         it.nd = 4;
-        const long ex[4] = {rows, np_, np_, np_}, so[4] = {np_ * pp, pp, np_, 1}, si[4] = {np_ * pp, np_, pp, 1};
+        const long ex[4] = {rows, np_, np_, np_}, so[4] = {np_ * ppad, ppad, np_, 1}, si[4] = {np_ * pp, np_, pp, 1};
         it.total = rows * np_ * pp;
         for (int i = 0; i < 4; ++i) {
           it.ext[i] = ex[i];
@@ -937,10 +941,10 @@ struct ric_ctx {
       GemmArgs g2;  // C[(c,e)][X] = 2 V2 . Bpp^T
       g2.M = (int)(rows * np_);
       g2.N = (int)nx;
-      g2.K = (int)pp;
+      g2.K = (int)ppad;
       g2.alpha = 2.0;
-      g2.lda = pp;
-      g2.ldb = pp;
+      g2.lda = ppad;
+      g2.ldb = ppad;
       g2.C = scrC.p;
       g2.ldc = nx;
       HIPCHK(ric::gemm_nt_f64(g2, wbuf.p, lgb.p, stream, scrK.p, scrK.n));
