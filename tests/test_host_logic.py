@@ -1,0 +1,80 @@
+"""Host-side logic that needs no GPU: the benchmark's flop count and the DIIS extrapolation."""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+def test_plan_flops_counts_contractions_dfc_and_ladder(tmp_path):
+    import bench
+    plan = tmp_path / "plan.txt"
+    plan.write_text("\n".join([
+        "SECTION residual",
+        "CONTRACT 1/1 R2:HHPP:0,1,2,3 T2:HHPP:0,1,4,5 t0:PPPP:4,5,2,3",      # 2 H^2 P^4
+        "DFC 1/1 t1:PP:0,3 B:XPP:X0,0,3 B:XCV:X0,1,2 T1:CV:1,2",             # through the factors
+        "LADDER R2 TAU",
+        "END",
+        "SECTION energy",
+        "CONTRACT 1/1 E::: T2:HHPP:0,1,2,3 T2:HHPP:0,1,2,3",
+        "END",
+    ]) + "\n")
+    nc, na, nv, nx = 2, 3, 5, 7
+    H, P, C, V = nc + na, na + nv, nc, nv
+    total, ladder = bench.plan_flops(nc, na, nv, nx, str(plan))
+    c2 = lambda n: n * (n - 1) / 2
+    lad = P ** 3 * (P + 1) * nx + 2 * (c2(P + 1) ** 2 * c2(H + 1) + c2(P) ** 2 * c2(H))
+    contract = 2.0 * H * H * P ** 4
+    # (pq|rs) y with y = T1[1,2]: Z[X] = sum_{1,2} B[X,1,2] T1[1,2], then t1 = sum_X B[X,0,3] Z[X]
+    dfc = 2.0 * nx * C * V + 2.0 * nx * P * P
+    build = 2.0 * nx * P * P * C * V + 2.0 * P * P * C * V
+    assert ladder == lad
+    assert total == pytest.approx(contract + min(dfc, build) + lad, rel=1e-12)
+
+
+class _HostCtx:
+    """The two vector calls DIIS makes, on host tensors (stands in for the library here)."""
+
+    def dot(self, a, b):
+        return float((a * b).sum())
+
+    def axpby(self, alpha, x, beta, y):
+        y.mul_(beta).add_(x, alpha=alpha)
+
+
+def test_diis_extrapolation_solves_a_linear_fixed_point():
+    """For a linear contraction map U(t) = M t + b, DIIS over enough iterates reaches the fixed
+    point far faster than plain iteration."""
+    from paper_2511_03567_amd.ric import _Diis
+    rng = np.random.default_rng(3)
+    n = 12
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    M = Q @ np.diag(np.linspace(0.5, 0.98, n)) @ Q.T
+    b = rng.standard_normal(n)
+    exact = np.linalg.solve(np.eye(n) - M, b)
+    to = lambda a: torch.from_numpy(a.copy())
+
+    def run(diis):
+        t1, t2 = torch.zeros(1, dtype=torch.float64), torch.zeros(n, dtype=torch.float64)
+        acc = _Diis(_HostCtx(), diis) if diis else None
+        for it in range(1, 500):
+            old = t2.clone()
+            t2 = to(M @ t2.numpy() + b)
+            step = float((t2 - old).norm())
+            if step < 1e-12:
+                return it, t2.numpy()
+            if acc is not None:
+                acc.push((t1.clone(), t2.clone()), (torch.zeros(1, dtype=torch.float64), old - t2))
+                acc.extrapolate(t1, t2)
+        return None, t2.numpy()
+
+    it_plain, x_plain = run(0)
+    it_diis, x_diis = run(n + 2)
+    assert it_diis is not None and np.abs(x_diis - exact).max() < 1e-9
+    assert it_plain is None or it_diis < it_plain / 4
