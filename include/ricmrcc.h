@@ -158,6 +158,15 @@ int ric_flow_fock_gradient(ric_ctx* ctx, const double* T1, const double* T2, con
  * f is overwritten and not loaded into the context (pass it to ric_load_fock). */
 int ric_build_fock(ric_ctx* ctx, const double* h, double* f);
 
+/* Semicanonical orbitals (Section 2.2: the denominators Delta are exact for a Fock matrix
+ * that is diagonal within the core, active and virtual blocks).  Diagonalizes those three
+ * blocks of the loaded f (rocSOLVER dsyevd on the device), and replaces the loaded f, DF
+ * factors and RDMs by their rotated forms: f' = U^T f U, B'[X] = U^T B[X] U, every RDM index
+ * rotated by the active block of U.  U (n x n, row-major, block-diagonal orthogonal; column
+ * j = new orbital j) is written to the caller; f_out (n x n, may be NULL) receives f'.
+ * Amplitudes of the old orbitals transform with the hole and particle blocks of U. */
+int ric_semicanonicalize(ric_ctx* ctx, double* U, double* f_out);
+
 /* ---- vector operations for accelerated iterations (DIIS) ------------------------------
  * The paper converges the amplitude equations with a DIIS-accelerated form of the iteration of
  * eq. cc-update (Section 2.2); these two calls are

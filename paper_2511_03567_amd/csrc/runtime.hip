@@ -21,6 +21,8 @@
 #include <unordered_map>
 #include <vector>
 
+#include <rocsolver/rocsolver.h>
+
 #include "../../include/ricmrcc.h"
 #include "gemm.h"
 #include "kernels.h"
@@ -227,6 +229,9 @@ struct ric_ctx {
   DevBuf f, eps, B, BT, BT32, g1, g2, g3, ga, ea, l2, k2, l3, k3, I4, I3, IJ, IK, tau, Edev, red, e0;
   DevBuf scrA, scrB, scrC, scrC2, scrK, wbuf, wbuf2, lad32, dfa, dfb, dfz, lgx, lgt, lgb, xr1, xl;
   Pool pool;
+  rocblas_handle solver = nullptr;  // created on first use (blockwise eigensolver)
+  const double* sc_B = nullptr;     // rotated quantities handed to the loaders by ric_semicanonicalize
+  std::vector<const double*> sc_g;
   int precision = RIC_FP64;
   double ladder_ms = 0.0, total_ms = 0.0;
   bool ladder_ran = false;
@@ -237,6 +242,7 @@ struct ric_ctx {
                       &tau, &Edev, &red, &e0, &scrA, &scrB, &scrC, &scrC2, &scrK, &wbuf, &wbuf2, &lad32, &dfa, &dfb, &dfz, &lgx, &lgt, &lgb, &xr1, &xl})
       b->release();
     pool.release();
+    if (solver) (void)rocblas_destroy_handle(solver);
     for (auto& e : ev)
       if (e) (void)hipEventDestroy(e);
   }
@@ -1610,6 +1616,168 @@ int ric_build_fock(ric_ctx* ctx, const double* h, double* f) {
       HIPCHK(ric::gemm_nt_f64(gk, ctx->scrC2.p, ctx->scrC.p, st, ctx->scrK.p, ctx->scrK.n));
     }
     HIPCHK(hipStreamSynchronize(st));
+  });
+}
+
+namespace {
+void copy2d(long rows, long cols, const double* in, long si0, long si1, double* out, long so0, long so1,
+            hipStream_t st) {
+  Iter it;
+  it.nd = 2;
+  it.ext[0] = rows;
+  it.ext[1] = cols;
+  it.si[0] = si0;
+  it.si[1] = si1;
+  it.so[0] = so0;
+  it.so[1] = so1;
+  it.total = rows * cols;
+  HIPCHK(ric::strided_copy(it, 1.0, in, 0.0, out, st));
+}
+
+// x[i_1..i_k] <- sum U[j_1][i_1] .. U[j_k][i_k] x[j_1..j_k] for an m^k tensor (ut = U^T, m x m):
+// k rounds of (contract the last index, then rotate it to the front)
+void rotate_all_indices(double* x, double* tmp, int m, int k, const double* ut, hipStream_t st, double* scr,
+                        size_t nscr) {
+  long rest = 1;
+  for (int i = 1; i < k; ++i) rest *= m;
+  for (int r = 0; r < k; ++r) {
+    GemmArgs g;
+    g.M = (int)rest;
+    g.N = m;
+    g.K = m;
+    g.lda = m;
+    g.ldb = m;
+    g.C = tmp;
+    g.ldc = m;
+    HIPCHK(ric::gemm_nt_f64(g, x, ut, st, scr, nscr));
+    copy2d(m, rest, tmp, 1, m, x, rest, 1, st);  // x[t'][rest] = tmp[rest][t']
+  }
+}
+}  // namespace
+
+int ric_semicanonicalize(ric_ctx* ctx, double* U, double* f_out) {
+  int rc = guard(ctx, [&] {
+    ctx->require_loaded();
+    if (!U) throw Err(RIC_E_ARG, "null U");
+    const int nc = ctx->sz.nc, na = ctx->sz.na, nv = ctx->sz.nv, nx = ctx->sz.naux;
+    const int n = nc + na + nv;
+    const long n2 = (long)n * n;
+    hipStream_t st = ctx->stream;
+    if (!ctx->solver) {
+      if (rocblas_create_handle(&ctx->solver) != rocblas_status_success) throw Err(RIC_E_HIP, "rocblas handle");
+    }
+    if (rocblas_set_stream(ctx->solver, st) != rocblas_status_success) throw Err(RIC_E_HIP, "rocblas stream");
+    ctx->release_scratch();
+    ctx->scrK.ensure(kSplitScratch);
+    double* scr = ctx->scrK.p;
+    const size_t nscr = ctx->scrK.n;
+    // U: eigenvectors of the core, active and virtual diagonal blocks of f
+    HIPCHK(ric::fill(U, n2, 0.0, st));
+    const int mmax = std::max(nc, std::max(na, nv));
+    ctx->scrA.ensure((size_t)mmax * mmax + 2 * mmax + 1);
+    double* blk = ctx->scrA.p;
+    double* ev = blk + (size_t)mmax * mmax;
+    double* off = ev + mmax;
+    rocblas_int* info = nullptr;
+    HIPCHK(hipMalloc(&info, sizeof(rocblas_int)));
+    const int o3[3] = {0, nc, nc + na}, m3[3] = {nc, na, nv};
+    for (int b = 0; b < 3; ++b) {
+      const int o = o3[b], m = m3[b];
+      if (m == 0) continue;
+      copy2d(m, m, ctx->f.p + (long)o * n + o, n, 1, blk, m, 1, st);
+      if (rocsolver_dsyevd(ctx->solver, rocblas_evect_original, rocblas_fill_upper, m, blk, m, ev, off, info) !=
+          rocblas_status_success)
+        throw Err(RIC_E_HIP, "rocsolver_dsyevd");
+      rocblas_int hinfo = 0;
+      HIPCHK(hipMemcpyAsync(&hinfo, info, sizeof(rocblas_int), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      if (hinfo != 0) throw Err(RIC_E_HIP, "eigensolver did not converge");
+      // column-major eigenvectors: U[o + i][o + j] = blk[j * m + i]
+      copy2d(m, m, blk, 1, m, U + (long)o * n + o, n, 1, st);
+    }
+    (void)hipFree(info);
+    ctx->scrB.ensure((size_t)n2 * 3);
+    double* Ut = ctx->scrB.p;
+    double* f1 = Ut + n2;
+    double* f1t = f1 + n2;
+    copy2d(n, n, U, 1, n, Ut, n, 1, st);
+    GemmArgs g;  // f1 = f U
+    g.M = n;
+    g.N = n;
+    g.K = n;
+    g.lda = n;
+    g.ldb = n;
+    g.ldc = n;
+    g.C = f1;
+    HIPCHK(ric::gemm_nt_f64(g, ctx->f.p, Ut, st, scr, nscr));
+    copy2d(n, n, f1, 1, n, f1t, n, 1, st);
+    ctx->scrC.ensure((size_t)n2);
+    g.C = ctx->scrC.p;  // f' = U^T f U
+    HIPCHK(ric::gemm_nt_f64(g, Ut, f1t, st, scr, nscr));
+    if (f_out) HIPCHK(hipMemcpyAsync(f_out, ctx->scrC.p, n2 * sizeof(double), hipMemcpyDeviceToDevice, st));
+    // B'[X] = U^T B[X] U
+    ctx->wbuf.ensure((size_t)nx * n2);
+    ctx->wbuf2.ensure((size_t)nx * n2);
+    GemmArgs gb;  // B1[(X,p)][q'] = sum_q B[X,p,q] U[q,q']
+    gb.M = nx * n;
+    gb.N = n;
+    gb.K = n;
+    gb.lda = n;
+    gb.ldb = n;
+    gb.ldc = n;
+    gb.C = ctx->wbuf.p;
+    HIPCHK(ric::gemm_nt_f64(gb, ctx->B.p, Ut, st, scr, nscr));
+    {  // B1t[X][q'][p] = B1[X][p][q']
+      Iter it;
+      it.nd = 3;
+      const long ex[3] = {nx, n, n}, so[3] = {n2, n, 1}, si[3] = {n2, 1, n};
+      it.total = (long)nx * n2;
+      for (int i = 0; i < 3; ++i) {
+        it.ext[i] = ex[i];
+        it.so[i] = so[i];
+        it.si[i] = si[i];
+      }
+      HIPCHK(ric::strided_copy(it, 1.0, ctx->wbuf.p, 0.0, ctx->wbuf2.p, st));
+    }
+    gb.C = ctx->wbuf.p;  // B'[X][q'][p'] = sum_p B1t[X][q'][p] U[p][p']
+    HIPCHK(ric::gemm_nt_f64(gb, ctx->wbuf2.p, Ut, st, scr, nscr));
+    // RDMs: every index rotated by the active block of U
+    double* ga1 = nullptr;
+    double* ga2 = nullptr;
+    double* ga3 = nullptr;
+    if (na > 0) {
+      const long a2 = (long)na * na, a4 = a2 * a2, a6 = a4 * a2;
+      ctx->dfa.ensure((size_t)(a2 + a4 + a6 + a2));
+      ctx->dfb.ensure((size_t)a6);
+      ga1 = ctx->dfa.p;
+      ga2 = ga1 + a2;
+      ga3 = ga2 + a4;
+      double* uat = ga3 + a6;
+      copy2d(na, na, Ut + (long)nc * n + nc, n, 1, uat, na, 1, st);
+      HIPCHK(hipMemcpyAsync(ga1, ctx->g1.p, a2 * 8, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(ga2, ctx->g2.p, a4 * 8, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(ga3, ctx->g3.p, a6 * 8, hipMemcpyDeviceToDevice, st));
+      rotate_all_indices(ga1, ctx->dfb.p, na, 2, uat, st, scr, nscr);
+      rotate_all_indices(ga2, ctx->dfb.p, na, 4, uat, st, scr, nscr);
+      rotate_all_indices(ga3, ctx->dfb.p, na, 6, uat, st, scr, nscr);
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    // load the rotated quantities (the copies go to the context's own buffers)
+    ctx->f.ensure(n2);
+    HIPCHK(hipMemcpyAsync(ctx->f.p, ctx->scrC.p, n2 * sizeof(double), hipMemcpyDeviceToDevice, st));
+    HIPCHK(ric::fock_diagonal(ctx->f.p, n, ctx->eps.p, st));
+    HIPCHK(hipStreamSynchronize(st));
+    ctx->sc_B = ctx->wbuf.p;
+    ctx->sc_g = {ga1, ga2, ga3};
+  });
+  if (rc != RIC_OK) return rc;
+  // outside the guard: the public loaders take the rotated copies
+  rc = ric_load_df(ctx, ctx->sc_B);
+  if (rc == RIC_OK && ctx->sz.na > 0) rc = ric_load_rdms(ctx, ctx->sc_g[0], ctx->sc_g[1], ctx->sc_g[2]);
+  ctx->sc_B = nullptr;
+  return guard(ctx, [&] {
+    if (rc != RIC_OK) throw Err(rc, ctx->err);
+    ctx->release_scratch();
   });
 }
 

@@ -61,6 +61,7 @@ def library():
     lib.ric_flow_scale.argtypes = [P, P, P, D, P, P]
     lib.ric_flow_fock_gradient.argtypes = [P] * 7 + [D, P]
     lib.ric_build_fock.argtypes = [P, P, P]
+    lib.ric_semicanonicalize.argtypes = [P, P, P]
     lib.ric_vec_dot.argtypes = [P, P, P, ctypes.c_long, ctypes.POINTER(D)]
     lib.ric_vec_axpby.argtypes = [P, D, P, D, P, ctypes.c_long]
     lib.ric_last_error.argtypes = [P]
@@ -68,7 +69,8 @@ def library():
     for fn in ("ric_create", "ric_set_spaces", "ric_load_fock", "ric_load_df", "ric_load_rdms",
                "ric_residual", "ric_update", "ric_energy", "ric_ladder", "ric_last_timings",
                "ric_adjoint_residual", "ric_energy_gradient", "ric_lambda_update", "ric_flow_scale",
-               "ric_flow_fock_gradient", "ric_vec_dot", "ric_vec_axpby", "ric_build_fock"):
+               "ric_flow_fock_gradient", "ric_vec_dot", "ric_vec_axpby", "ric_build_fock",
+               "ric_semicanonicalize"):
         getattr(lib, fn).restype = I
     _lib = lib
     return lib
@@ -206,6 +208,13 @@ class Context:
     def build_fock(self, h, f):
         """Generalized Fock matrix f from h with the loaded DF factors and RDMs (not loaded)."""
         self._check(self.lib.ric_build_fock(self.h, _ptr(h, (self.n, self.n), "h"), _ptr(f, (self.n, self.n), "f")))
+
+    def semicanonicalize(self):
+        """Rotate the loaded f, B and RDMs to semicanonical orbitals; returns (U, f')."""
+        U = torch.empty((self.n, self.n), dtype=torch.float64, device=self.device)
+        f = torch.empty_like(U)
+        self._check(self.lib.ric_semicanonicalize(self.h, _ptr(U, U.shape, "U"), _ptr(f, f.shape, "f")))
+        return U, f
 
     # --- vector operations (DIIS) --------------------------------------------------------
     def dot(self, a, b):

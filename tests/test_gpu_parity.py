@@ -194,3 +194,40 @@ def test_fock_from_core_hamiltonian(name, cfg):
     f = torch.zeros((cfg.n, cfg.n), dtype=torch.float64, device="cuda")
     ctx.build_fock(t(h), f)
     assert _rel(f.cpu().numpy(), inp.f) < 1e-12
+
+
+@pytest.mark.parametrize("name,cfg", [CASES[1], CASES[3], ("single reference nc4 nv9 naux20", CASES[2][1])],
+                         ids=["cas44", "nocore", "sr"])
+def test_semicanonical_rotation_is_covariant(name, cfg):
+    """After semicanonicalization (block-diagonal orthogonal U), the residual at the rotated
+    amplitudes is the rotated residual and the energy is unchanged (block-rotation covariance
+    of the residual and energy functions); f' is diagonal within the core, active and virtual
+    blocks and equals U^T f U."""
+    print(f"semicanonical {name}", flush=True)
+    inp = S.make_inputs(cfg)
+    nc, na, nv = cfg.nc, cfg.na, cfg.nv
+    nH, nP, n = nc + na, na + nv, cfg.n
+    T1, T2 = _amps(cfg, 31)
+    ctx, t = _ctx(cfg, inp)
+    R1 = torch.zeros((nH, nP), dtype=torch.float64, device="cuda")
+    R2 = torch.zeros((nH, nH, nP, nP), dtype=torch.float64, device="cuda")
+    ctx.residual(t(T1), t(T2), R1, R2)
+    e, _ = ctx.energy(t(T1), t(T2))
+    U, fr = ctx.semicanonicalize()
+    U, fr = U.cpu().numpy(), fr.cpu().numpy()
+    assert np.abs(U.T @ U - np.eye(n)).max() < 1e-12
+    assert np.abs(fr - U.T @ inp.f @ U).max() < 1e-12 * max(1.0, np.abs(inp.f).max())
+    for a, b in ((0, nc), (nc, nc + na), (nc + na, n)):
+        blk = fr[a:b, a:b]
+        assert np.abs(blk - np.diag(np.diag(blk))).max(initial=0.0) < 1e-10
+        assert np.abs(U[a:b, :a]).max(initial=0.0) == 0.0 and np.abs(U[a:b, b:]).max(initial=0.0) == 0.0
+    uh, up = U[:nH, :nH], U[nc:, nc:]
+    rot1 = lambda x: uh.T @ x @ up
+    rot2 = lambda x: np.einsum("kK,lL,cC,dD,klcd->KLCD", uh, uh, up, up, x, optimize=True)
+    S1 = torch.zeros_like(R1)
+    S2 = torch.zeros_like(R2)
+    ctx.residual(t(rot1(T1)), t(rot2(T2)), S1, S2)
+    e2, _ = ctx.energy(t(rot1(T1)), t(rot2(T2)))
+    assert _rel(S1.cpu().numpy(), rot1(R1.cpu().numpy())) < 1e-10
+    assert _rel(S2.cpu().numpy(), rot2(R2.cpu().numpy())) < 1e-10
+    assert abs(e2 - e) < 1e-10
