@@ -275,6 +275,37 @@ def project_singlet(rng: np.random.Generator, na: int):
     return dets, c / np.linalg.norm(c)
 
 
+def spin_lower(dets, coeffs, na: int):
+    """S_- |Psi> with S_- = sum_p a^+_{p beta} a_{p alpha}; returns (dets, coeffs)."""
+    out = {}
+    for d, c in zip(dets, coeffs):
+        d = int(d)
+        for p in range(na):
+            oa, ob = p, na + p
+            if not (d >> oa) & 1 or (d >> ob) & 1:
+                continue
+            s = (-1) ** bin(d & ((1 << oa) - 1)).count("1")
+            d1 = d ^ (1 << oa)
+            s *= (-1) ** bin(d1 & ((1 << ob) - 1)).count("1")
+            d1 |= 1 << ob
+            out[d1] = out.get(d1, 0.0) + s * float(c)
+    keys = sorted(out)
+    return np.array(keys, dtype=np.uint64), np.array([out[k] for k in keys])
+
+
+def random_triplet(rng: np.random.Generator, na: int):
+    """A random normalized S = 1, M_S = 1 vector of CAS(na, na) and its M_S = 0 partner
+    S_-|Psi> / |S_-|Psi>| (dense; small na only).  Returns ((dets1, c1), (dets0, c0))."""
+    dets = cas_determinants(na, na // 2 + 1, na - na // 2 - 1)
+    S2 = _s2_matrix(dets, na)
+    w, V = np.linalg.eigh(S2)
+    sub = V[:, np.abs(w - 2.0) < 1e-8]
+    c = sub @ rng.standard_normal(sub.shape[1])
+    c = c / np.linalg.norm(c)
+    d0, c0 = spin_lower(dets, c, na)
+    return (dets, c), (d0, c0 / np.linalg.norm(c0))
+
+
 def make_inputs(cfg: Config, with_rdms: bool = True) -> Inputs:
     rng = np.random.default_rng(cfg.seed)
     f = make_fock(rng, cfg.nc, cfg.na, cfg.nv)

@@ -231,3 +231,36 @@ def test_semicanonical_rotation_is_covariant(name, cfg):
     assert _rel(S1.cpu().numpy(), rot1(R1.cpu().numpy())) < 1e-10
     assert _rel(S2.cpu().numpy(), rot2(R2.cpu().numpy())) < 1e-10
     assert abs(e2 - e) < 1e-10
+
+
+def test_triplet_reference_matches_oracle():
+    """A triplet reference: spin-free RDMs of the M_S = 1 component (equal to those of M_S = 0),
+    unchanged equations; the GPU residual and energy match the oracle."""
+    nc, na, nv, naux = 2, 4, 12, 30
+    cfg = S.custom_config("trip", nc, na, nv, naux, 47)
+    inp = S.make_inputs(cfg, with_rdms=False)
+    (d1, c1), (d0, c0) = S.random_triplet(np.random.default_rng(48), na)
+    G = S.spinfree_rdms(d1, c1, na, 3)
+    G0 = S.spinfree_rdms(d0, c0, na, 3)
+    from paper_2511_03567_amd import ric
+    dev = torch.device("cuda", 0)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    T1, T2 = _amps(cfg, 49)
+    nH, nP = nc + na, na + nv
+    out = []
+    for GG in (G, G0):
+        ctx = ric.Context(0)
+        ctx.set_spaces(nc, na, nv, naux)
+        ctx.load_fock(t(inp.f))
+        ctx.load_df(t(inp.B))
+        ctx.load_rdms(*(t(g) for g in GG))
+        R1 = torch.zeros((nH, nP), dtype=torch.float64, device=dev)
+        R2 = torch.zeros((nH, nH, nP, nP), dtype=torch.float64, device=dev)
+        ctx.residual(t(T1), t(T2), R1, R2)
+        e, _ = ctx.energy(t(T1), t(T2))
+        out.append((R1.cpu().numpy(), R2.cpu().numpy(), e))
+    ref = R.Reference(nc, na, nv, inp.f, inp.B, *G)
+    r1, r2 = ref.residual(T1, T2)
+    assert _rel(out[0][0], r1) < RTOL and _rel(out[0][1], r2) < RTOL
+    assert abs(out[0][2] - ref.energy(T1, T2)) < ETOL
+    assert _rel(out[1][1], out[0][1]) < 1e-12 and abs(out[1][2] - out[0][2]) < 1e-12
