@@ -305,6 +305,12 @@ def main():
         out["fp32mix_residual_max_rel_diff"] = diff / scale
         out["fp32mix_ladder_tflops"] = lflops / (lm / 1e3) / 1e12 if lm > 0 else None
         out["fp32mix_ladder_frac_of_fp32_peak"] = (lflops / (lm / 1e3) / 1e12) / PEAK_FP32 if lm > 0 else None
+    # energy functional at the starting amplitudes (FP64), timed once
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.energy(T1s, T2s)
+    out["energy_s"] = time.perf_counter() - t0
+    log(f"energy done: {out['energy_s']:.2f} s")
     if not args.no_mixed and not args.no_converge:
         # converged energies, FP32-mixed iterations + FP64 polish against FP64 throughout, at the
         # CAS(8,8) shape (nc=10, nv=120, naux=360; s = 0.5 and 1.0, DIIS over 6 iterates); a
