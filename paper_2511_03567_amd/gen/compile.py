@@ -632,13 +632,19 @@ def _emit_groups(plan, groups):
         # tensors with the same X pattern share X; their Z's are summed first
         sub = OrderedDict()
         rest_members = []
+        def is_tmp(o):
+            return o.name == "?" or (o.name.startswith("t") and o.name[1:].isdigit())
+
         for m in members:
             coef, ysteps, Yop, ylabs, P0m, ext, out_ranges, rng, ren, g = m
-            if len(ysteps) == 1:
-                a, b, new = ysteps[0]
+            if ysteps:
+                # the member's intermediate is X * Z with X stored; Z is stored too (one step) or
+                # computed by the member's earlier steps (the prefix), which then accumulate it
+                a, b, new = ysteps[-1]
+                prefix = ysteps[:-1]
                 placed = False
                 for X, Z in ((a, b), (b, a)):
-                    if X.name.startswith("t") or Z.name.startswith("t") and Z.name[1:].isdigit():
+                    if is_tmp(X) or (is_tmp(Z) if not prefix else Z.name != "?"):
                         continue
                     # roles: labels of Y map to their canonical names in the group
                     yrole = {l: ren.get(l, None) for l in ylabs}
@@ -650,7 +656,7 @@ def _emit_groups(plan, groups):
                     zlabs = sorted(Z.labels, key=lambda l: (yrole.get(l) or iren[l]))
                     zkey = tuple((yrole.get(l) or iren[l], _widen(rng[l])) for l in zlabs)
                     key2 = (X.name, xkey, zkey)
-                    sub.setdefault(key2, []).append((coef, X, Z, zlabs, rng, ylabs, m))
+                    sub.setdefault(key2, []).append((coef, X, Z, zlabs, rng, ylabs, m, prefix))
                     placed = True
                     break
                 if placed:
@@ -660,13 +666,17 @@ def _emit_groups(plan, groups):
             if len(items) == 1:
                 rest_members.append(items[0][6])
                 continue
-            coef0_, X0, Z0, zl0, rng0_, yl0, m0 = items[0]
+            coef0_, X0, Z0, zl0, rng0_, yl0, m0, _ = items[0]
             yl0 = order(yl0, m0[8])
             zr = [_widen(rng0_[l]) for l in zl0]
             zacc = plan.new_tmp(zr)
             plan.lines.append(f"ZERO {zacc}")
-            for coef, X, Z, zlabs, rng, ylabs, m in items:
-                plan.add(Operand(zacc, [rng[l] for l in zlabs], zlabs), coef, Z)
+            for coef, X, Z, zlabs, rng, ylabs, m, prefix in items:
+                zop = Operand(zacc, [rng[l] for l in zlabs], zlabs)
+                if prefix:
+                    _emit_steps(plan, prefix, final_out=zop, alpha=coef)
+                else:
+                    plan.add(zop, coef, Z)
             # X over the ranges of the first member, its inner labels widened like Z
             xr = [(_widen(r) if (l in zl0 and l not in yl0) else r) for l, r in zip(X0.labels, X0.ranges)]
             Xop = Operand(X0.name, xr, X0.labels)
