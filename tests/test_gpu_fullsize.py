@@ -1,0 +1,95 @@
+"""Full-size parity: the 809-orbital CAS(12,12) workload (nc=40, nv=757, naux=2200, the
+benchmark's shapes and launch configuration) against the oracle on sampled outputs.
+
+The amplitudes vanish outside a few cores and virtuals spread over the index ranges
+(first and last orbitals, both sides of the 128-wide tile edge, the lone particle of the
+ragged last tile, interior ones).  Every residual element whose indices lie in those
+cores + all actives + those virtuals, and the correlation energy, then equal the
+oracle's on the problem restricted to those orbitals; test_subset_cpu.py checks that
+reduction with the oracle alone.  Bar: 1e-10 relative on the residuals, 1e-9 E_h on
+the energy.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import synthetic as S
+from oracle import ricmrcc as R
+
+import orbital_subset as OS
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+CORES = [0, 21, 38, 39]
+VIRTS = [0, 115, 116, 390, 755, 756]     # particle positions 12, 127, 128, 402, 767, 768 of 769
+
+
+@pytest.mark.timeout(900)
+def test_fullsize_residual_and_energy_sampled():
+    from paper_2511_03567_amd import ric
+    cfg = S.CONFIGS["b12_cas1212"]
+    nc, na, nv = cfg.nc, cfg.na, cfg.nv
+    t0 = time.perf_counter()
+    print(f"full size {cfg.name}: nc={nc} na={na} nv={nv} naux={cfg.naux}, cores {CORES}, virtuals {VIRTS}",
+          flush=True)
+    inp = S.make_inputs(cfg)
+    fs, Bs = OS.restrict(inp.f, inp.B, nc, na, CORES, VIRTS)
+    hm, pm = OS.hole_map(nc, na, CORES), OS.particle_map(na, VIRTS)
+    ncs, nvs = len(CORES), len(VIRTS)
+    rng = np.random.default_rng(11)
+    m1, m2 = R.block_mask(ncs, na, nvs)
+    T1s = rng.standard_normal((ncs + na, na + nvs)) * 0.05 * m1
+    T2s = rng.standard_normal((ncs + na,) * 2 + (na + nvs,) * 2) * 0.05
+    T2s = 0.5 * (T2s + T2s.transpose(1, 0, 3, 2)) * m2
+    print(f"  inputs in {time.perf_counter() - t0:.1f} s", flush=True)
+
+    dev = torch.device("cuda", 0)
+    ctx = ric.Context(0)
+    ctx.set_spaces(nc, na, nv, cfg.naux)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    ctx.load_fock(t(inp.f))
+    Bd = t(inp.B)
+    ctx.load_df(Bd)
+    del Bd
+    ctx.load_rdms(t(inp.G1), t(inp.G2), t(inp.G3))
+    G1, G2, G3 = inp.G1, inp.G2, inp.G3
+    del inp
+    s1, s2 = ctx.amplitude_shapes()
+    h = torch.as_tensor(hm, device=dev)
+    p = torch.as_tensor(pm, device=dev)
+    i1 = (h[:, None], p[None, :])
+    i2 = (h[:, None, None, None], h[None, :, None, None], p[None, None, :, None], p[None, None, None, :])
+    T1 = torch.zeros(s1, dtype=torch.float64, device=dev)
+    T2 = torch.zeros(s2, dtype=torch.float64, device=dev)
+    T1[i1] = t(T1s)
+    T2[i2] = t(T2s)
+    R1 = torch.full(s1, 7.0, dtype=torch.float64, device=dev)
+    R2 = torch.full(s2, 7.0, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    print("  FP64 residual at full size", flush=True)
+    ctx.residual(T1, T2, R1, R2, ric.RIC_FP64)
+    torch.cuda.synchronize()
+    R1g = R1[i1].cpu().numpy()
+    R2g = R2[i2].cpu().numpy()
+    del R1, R2
+    print("  energy at full size", flush=True)
+    e, _ = ctx.energy(T1, T2)
+    ctx.close()
+    del T1, T2
+    torch.cuda.empty_cache()
+    print(f"  GPU done at {time.perf_counter() - t0:.1f} s; oracle on the {ncs}-core {nvs}-virtual subset",
+          flush=True)
+
+    sub = R.Reference(ncs, na, nvs, fs, Bs, G1, G2, G3)
+    R1o, R2o = sub.residual(T1s, T2s)
+    r1 = float(np.abs(R1g - R1o).max() / max(1.0, np.abs(R1o).max()))
+    r2 = float(np.abs(R2g - R2o).max() / max(1.0, np.abs(R2o).max()))
+    print(f"  residual rel diff R1 {r1:.2e} R2 {r2:.2e}", flush=True)
+    eo = sub.energy(T1s, T2s)
+    print(f"  energy {e:.12f} oracle {eo:.12f} |dE| {abs(e - eo):.2e}; {time.perf_counter() - t0:.1f} s",
+          flush=True)
+    assert r1 < 1e-10 and r2 < 1e-10
+    assert abs(e - eo) < 1e-9
