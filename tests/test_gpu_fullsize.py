@@ -6,7 +6,8 @@ The amplitudes vanish outside a few cores and virtuals spread over the index ran
 ragged last tile, interior ones).  Every residual element whose indices lie in those
 cores + all actives + those virtuals, and the correlation energy, then equal the
 oracle's on the problem restricted to those orbitals; test_subset_cpu.py checks that
-reduction with the oracle alone.  Bar: 1e-10 relative on the residuals, 1e-9 E_h on
+reduction with the oracle alone.  Bar: 1e-10 relative on the FP64 residuals, 1e-5 on
+the FP32-mixed residuals (FP32 MFMA tiles with FP64 accumulation per slab), 1e-9 E_h on
 the energy.
 """
 import time
@@ -74,6 +75,13 @@ def test_fullsize_residual_and_energy_sampled():
     torch.cuda.synchronize()
     R1g = R1[i1].cpu().numpy()
     R2g = R2[i2].cpu().numpy()
+    print("  FP32-mixed residual at full size", flush=True)
+    R1.fill_(7.0)
+    R2.fill_(7.0)
+    ctx.residual(T1, T2, R1, R2, ric.RIC_FP32MIX)
+    torch.cuda.synchronize()
+    R1m = R1[i1].cpu().numpy()
+    R2m = R2[i2].cpu().numpy()
     del R1, R2
     print("  energy at full size", flush=True)
     e, _ = ctx.energy(T1, T2)
@@ -87,9 +95,12 @@ def test_fullsize_residual_and_energy_sampled():
     R1o, R2o = sub.residual(T1s, T2s)
     r1 = float(np.abs(R1g - R1o).max() / max(1.0, np.abs(R1o).max()))
     r2 = float(np.abs(R2g - R2o).max() / max(1.0, np.abs(R2o).max()))
-    print(f"  residual rel diff R1 {r1:.2e} R2 {r2:.2e}", flush=True)
+    m1 = float(np.abs(R1m - R1o).max() / max(1.0, np.abs(R1o).max()))
+    m2 = float(np.abs(R2m - R2o).max() / max(1.0, np.abs(R2o).max()))
+    print(f"  residual rel diff FP64: R1 {r1:.2e} R2 {r2:.2e}; FP32-mixed: R1 {m1:.2e} R2 {m2:.2e}", flush=True)
     eo = sub.energy(T1s, T2s)
     print(f"  energy {e:.12f} oracle {eo:.12f} |dE| {abs(e - eo):.2e}; {time.perf_counter() - t0:.1f} s",
           flush=True)
     assert r1 < 1e-10 and r2 < 1e-10
+    assert m1 < 1e-5 and m2 < 1e-5
     assert abs(e - eo) < 1e-9
