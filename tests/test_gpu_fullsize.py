@@ -9,6 +9,12 @@ oracle's on the problem restricted to those orbitals; test_subset_cpu.py checks 
 reduction with the oracle alone.  Bar: 1e-10 relative on the FP64 residuals, 1e-5 on
 the FP32-mixed residuals (FP32 MFMA tiles with FP64 accumulation per slab), 1e-9 E_h on
 the energy.
+
+The adjoint (dT = J_r^T x) reduces the same way when x also vanishes outside the subset:
+along amplitude directions inside the subset the full residual and the restricted one are
+the same function.  Its subset part is checked by a dot-product test <x, J v> = <dT, v>
+against central differences of the oracle on the subset, exact up to rounding because the
+residual is quadratic in T.
 """
 import time
 
@@ -104,3 +110,83 @@ def test_fullsize_residual_and_energy_sampled():
     assert r1 < 1e-10 and r2 < 1e-10
     assert m1 < 1e-5 and m2 < 1e-5
     assert abs(e - eo) < 1e-9
+
+
+CORES_ADJ = [0, 39]
+VIRTS_ADJ = [115, 116, 756]
+H = 1e-3
+
+
+def _sym(rng, nh, np_, m2, scale):
+    x = rng.standard_normal((nh, nh, np_, np_)) * scale
+    return 0.5 * (x + x.transpose(1, 0, 3, 2)) * m2
+
+
+@pytest.mark.timeout(900)
+def test_fullsize_adjoint_residual_sampled():
+    from paper_2511_03567_amd import ric
+    cfg = S.CONFIGS["b12_cas1212"]
+    nc, na, nv = cfg.nc, cfg.na, cfg.nv
+    t0 = time.perf_counter()
+    print(f"full-size adjoint {cfg.name}: cores {CORES_ADJ}, virtuals {VIRTS_ADJ}", flush=True)
+    inp = S.make_inputs(cfg)
+    fs, Bs = OS.restrict(inp.f, inp.B, nc, na, CORES_ADJ, VIRTS_ADJ)
+    hm, pm = OS.hole_map(nc, na, CORES_ADJ), OS.particle_map(na, VIRTS_ADJ)
+    ncs, nvs = len(CORES_ADJ), len(VIRTS_ADJ)
+    nhs, nps = ncs + na, na + nvs
+    rng = np.random.default_rng(12)
+    m1, m2 = R.block_mask(ncs, na, nvs)
+    T = (rng.standard_normal((nhs, nps)) * 0.05 * m1, _sym(rng, nhs, nps, m2, 0.05))
+    x = (rng.standard_normal((nhs, nps)) * m1, _sym(rng, nhs, nps, m2, 1.0))
+    v = (rng.standard_normal((nhs, nps)) * m1, _sym(rng, nhs, nps, m2, 1.0))
+
+    dev = torch.device("cuda", 0)
+    ctx = ric.Context(0)
+    ctx.set_spaces(nc, na, nv, cfg.naux)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    ctx.load_fock(t(inp.f))
+    Bd = t(inp.B)
+    ctx.load_df(Bd)
+    del Bd
+    ctx.load_rdms(t(inp.G1), t(inp.G2), t(inp.G3))
+    G = (inp.G1, inp.G2, inp.G3)
+    del inp
+    s1, s2 = ctx.amplitude_shapes()
+    h = torch.as_tensor(hm, device=dev)
+    p = torch.as_tensor(pm, device=dev)
+    i1 = (h[:, None], p[None, :])
+    i2 = (h[:, None, None, None], h[None, :, None, None], p[None, None, :, None], p[None, None, None, :])
+
+    def full(a1, a2):
+        b1 = torch.zeros(s1, dtype=torch.float64, device=dev)
+        b2 = torch.zeros(s2, dtype=torch.float64, device=dev)
+        b1[i1] = t(a1)
+        b2[i2] = t(a2)
+        return b1, b2
+
+    T1, T2 = full(*T)
+    X1, X2 = full(*x)
+    dT1 = torch.full(s1, 7.0, dtype=torch.float64, device=dev)
+    dT2 = torch.full(s2, 7.0, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    print(f"  inputs in {time.perf_counter() - t0:.1f} s; adjoint residual at full size", flush=True)
+    ctx.adjoint_residual(T1, T2, X1, X2, dT1, dT2)
+    torch.cuda.synchronize()
+    d1 = dT1[i1].cpu().numpy()
+    d2 = dT2[i2].cpu().numpy()
+    sym = bool(torch.equal(dT2, dT2.permute(1, 0, 3, 2)))
+    masked = bool(torch.all(dT2[nc:, nc:, :na, :na] == 0.0))
+    ctx.close()
+    del T1, T2, X1, X2, dT1, dT2
+    torch.cuda.empty_cache()
+    print(f"  GPU done at {time.perf_counter() - t0:.1f} s; oracle differences on the subset", flush=True)
+
+    sub = R.Reference(ncs, na, nvs, fs, Bs, *G)
+    rp = sub.residual(T[0] + H * v[0], T[1] + H * v[1])
+    rm = sub.residual(T[0] - H * v[0], T[1] - H * v[1])
+    want = float(sum(np.sum(a * (b - c)) for a, b, c in zip(x, rp, rm)) / (2 * H))
+    got = float(np.sum(d1 * v[0]) + np.sum(d2 * v[1]))
+    print(f"  <dT, v> {got:.12e}  <x, J v> {want:.12e}  rel {abs(got - want) / max(1.0, abs(want)):.2e}; "
+          f"{time.perf_counter() - t0:.1f} s", flush=True)
+    assert abs(got - want) <= 1e-9 * max(1.0, abs(want))
+    assert sym and masked
