@@ -8,7 +8,8 @@ cores + all actives + those virtuals, and the correlation energy, then equal the
 oracle's on the problem restricted to those orbitals; test_subset_cpu.py checks that
 reduction with the oracle alone.  Bar: 1e-10 relative on the FP64 residuals, 1e-5 on
 the FP32-mixed residuals (FP32 MFMA tiles with FP64 accumulation per slab), 1e-9 E_h on
-the energy.
+the energy.  The regularized update, elementwise in the diagonal of f, is checked on the
+same elements against the oracle's update of the sampled residual, to 1e-14.
 
 The adjoint (dT = J_r^T x) reduces the same way when x also vanishes outside the subset:
 along amplitude directions inside the subset the full residual and the restricted one are
@@ -76,21 +77,25 @@ def test_fullsize_residual_and_energy_sampled():
     R1 = torch.full(s1, 7.0, dtype=torch.float64, device=dev)
     R2 = torch.full(s2, 7.0, dtype=torch.float64, device=dev)
     torch.cuda.synchronize()
+    print("  energy at full size", flush=True)
+    e, _ = ctx.energy(T1, T2)
+    print("  FP32-mixed residual at full size", flush=True)
+    ctx.residual(T1, T2, R1, R2, ric.RIC_FP32MIX)
+    torch.cuda.synchronize()
+    R1m = R1[i1].cpu().numpy()
+    R2m = R2[i2].cpu().numpy()
+    R1.fill_(7.0)
+    R2.fill_(7.0)
     print("  FP64 residual at full size", flush=True)
     ctx.residual(T1, T2, R1, R2, ric.RIC_FP64)
     torch.cuda.synchronize()
     R1g = R1[i1].cpu().numpy()
     R2g = R2[i2].cpu().numpy()
-    print("  FP32-mixed residual at full size", flush=True)
-    R1.fill_(7.0)
-    R2.fill_(7.0)
-    ctx.residual(T1, T2, R1, R2, ric.RIC_FP32MIX)
-    torch.cuda.synchronize()
-    R1m = R1[i1].cpu().numpy()
-    R2m = R2[i2].cpu().numpy()
+    print("  regularized update at full size", flush=True)
+    ctx.update(T1, T2, R1, R2, cfg.s)
+    U1 = T1[i1].cpu().numpy()
+    U2 = T2[i2].cpu().numpy()
     del R1, R2
-    print("  energy at full size", flush=True)
-    e, _ = ctx.energy(T1, T2)
     ctx.close()
     del T1, T2
     torch.cuda.empty_cache()
@@ -101,14 +106,21 @@ def test_fullsize_residual_and_energy_sampled():
     R1o, R2o = sub.residual(T1s, T2s)
     r1 = float(np.abs(R1g - R1o).max() / max(1.0, np.abs(R1o).max()))
     r2 = float(np.abs(R2g - R2o).max() / max(1.0, np.abs(R2o).max()))
-    m1 = float(np.abs(R1m - R1o).max() / max(1.0, np.abs(R1o).max()))
-    m2 = float(np.abs(R2m - R2o).max() / max(1.0, np.abs(R2o).max()))
-    print(f"  residual rel diff FP64: R1 {r1:.2e} R2 {r2:.2e}; FP32-mixed: R1 {m1:.2e} R2 {m2:.2e}", flush=True)
+    x1 = float(np.abs(R1m - R1o).max() / max(1.0, np.abs(R1o).max()))
+    x2 = float(np.abs(R2m - R2o).max() / max(1.0, np.abs(R2o).max()))
+    print(f"  residual rel diff FP64: R1 {r1:.2e} R2 {r2:.2e}; FP32-mixed: R1 {x1:.2e} R2 {x2:.2e}", flush=True)
     eo = sub.energy(T1s, T2s)
     print(f"  energy {e:.12f} oracle {eo:.12f} |dE| {abs(e - eo):.2e}; {time.perf_counter() - t0:.1f} s",
           flush=True)
+    D1, D2 = R.denominators(fs, ncs, na, nvs)
+    N1 = R.ric_update(T1s, R1g, D1, cfg.s) * m1
+    N2 = R.ric_update(T2s, R2g, D2, cfg.s) * m2
+    u1 = float(np.abs(U1 - N1).max() / max(1.0, np.abs(N1).max()))
+    u2 = float(np.abs(U2 - N2).max() / max(1.0, np.abs(N2).max()))
+    print(f"  update rel diff T1 {u1:.2e} T2 {u2:.2e}", flush=True)
     assert r1 < 1e-10 and r2 < 1e-10
-    assert m1 < 1e-5 and m2 < 1e-5
+    assert x1 < 1e-5 and x2 < 1e-5
+    assert u1 < 1e-14 and u2 < 1e-14
     assert abs(e - eo) < 1e-9
 
 
