@@ -533,39 +533,50 @@ __global__ void pack_tau_kernel(const double* __restrict__ tau, int nh, int np, 
 }
 
 // W+[(c,d)][ef] = W'[c][e][d][f] + W'[c][f][d][e] (e >= f), W-[(c,d)][ef] = difference (e > f),
-// for c in [c0, c1), d < c1; W' rows (c, e) of length c1 * np
+// for c in [c0, c1), d < c1; W' rows (c, e) of length c1 * np.  For one pair (c, d) the
+// np x np matrix M[e][f] = W'[c][e][d][f] is read as 32 x 32 tiles: a workgroup loads the
+// tile (E, F), E >= F, and its mirror (F, E) with row-contiguous reads into LDS, so that
+// M[f][e] comes from LDS instead of a column walk through HBM, and writes the packed
+// triangles row by row.  grid.x: tile pairs, grid.y: (c, d) pairs.
+constexpr int kPackTile = 32;
+
 template <typename T>
-__global__ void pack_w_kernel(const T* __restrict__ wsrc, int np, int rows, int c1, T* __restrict__ wp,
-                              T* __restrict__ wm, long ldp, long ldm) {
+__global__ void __launch_bounds__(256) pack_w_kernel(const T* __restrict__ wsrc, int np, long pairs, int c1,
+                                                     T* __restrict__ wp, T* __restrict__ wm, long ldp, long ldm) {
+  constexpr int TS = kPackTile;
+  __shared__ T tile[2][TS][TS + 1];
   const long npp = (long)np * (np + 1) / 2, npm = (long)np * (np - 1) / 2;
-  const long pairs = (long)rows * c1;
-  const long total = pairs * (ldp + ldm);
+  const int tp = blockIdx.x;
+  int E = (int)((sqrt(8.0 * tp + 1.0) - 1.0) / 2.0);
+  while (E * (E + 1) / 2 > tp) --E;
+  while ((E + 1) * (E + 2) / 2 <= tp) ++E;
+  const int F = tp - E * (E + 1) / 2;
   const long ld = (long)c1 * np;
-  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
-    const bool plus = t < pairs * ldp;
-    const long u = plus ? t : t - pairs * ldp;
-    const long ldq = plus ? ldp : ldm;
-    const long pr = u / ldq, q = u % ldq;
-    if (q >= (plus ? npp : npm)) {
-      if (plus) wp[u] = (T)0; else wm[u] = (T)0;
-      continue;
-    }
-    const int cr = (int)(pr / c1), d = (int)(pr % c1);
-    int e;
-    if (plus) {
-      e = (int)((sqrt(8.0 * q + 1.0) - 1.0) / 2.0);
-      while ((long)e * (e + 1) / 2 > q) --e;
-      while ((long)(e + 1) * (e + 2) / 2 <= q) ++e;
-    } else {
-      e = (int)((sqrt(8.0 * q + 1.0) + 1.0) / 2.0);
-      while ((long)e * (e - 1) / 2 > q) --e;
-      while ((long)(e + 1) * e / 2 <= q) ++e;
-    }
-    const int f = plus ? (int)(q - (long)e * (e + 1) / 2) : (int)(q - (long)e * (e - 1) / 2);
-    const T a = wsrc[((long)cr * np + e) * ld + (long)d * np + f];
-    const T b = wsrc[((long)cr * np + f) * ld + (long)d * np + e];
-    if (plus) wp[u] = a + b;
-    else wm[u] = a - b;
+  const int tx = threadIdx.x % TS, ty = threadIdx.x / TS;
+  constexpr int kRowsPerPass = 256 / TS;
+  for (long pr = blockIdx.y; pr < pairs; pr += gridDim.y) {   // block-uniform: the barriers below are safe
+  const int cr = (int)(pr / c1), d = (int)(pr % c1);
+  const T* base = wsrc + (long)cr * np * ld + (long)d * np;   // M[e][f] = base[e * ld + f]
+  for (int i = ty; i < TS; i += kRowsPerPass) {
+    const int e = E * TS + i, f = F * TS + tx;
+    tile[0][i][tx] = (e < np && f < np) ? base[(long)e * ld + f] : (T)0;        // M[E*TS+i][F*TS+tx]
+    const int e2 = F * TS + i, f2 = E * TS + tx;
+    tile[1][i][tx] = (e2 < np && f2 < np) ? base[(long)e2 * ld + f2] : (T)0;    // M[F*TS+i][E*TS+tx]
+  }
+  __syncthreads();
+  for (int i = ty; i < TS; i += kRowsPerPass) {
+    const int e = E * TS + i, f = F * TS + tx;
+    if (e >= np || f > e) continue;
+    const T a = tile[0][i][tx];    // M[e][f]
+    const T b = tile[1][tx][i];    // M[f][e]
+    wp[pr * ldp + (long)e * (e + 1) / 2 + f] = a + b;
+    if (f < e) wm[pr * ldm + (long)e * (e - 1) / 2 + f] = a - b;
+  }
+  if (tp == 0) {
+    for (long q = npp + threadIdx.x; q < ldp; q += blockDim.x) wp[pr * ldp + q] = (T)0;
+    for (long q = npm + threadIdx.x; q < ldm; q += blockDim.x) wm[pr * ldm + q] = (T)0;
+  }
+  __syncthreads();   // the next pair overwrites the tiles
   }
 }
 
@@ -749,20 +760,26 @@ hipError_t pack_tau_f32(const double* tau, int nh, int np, float* tp, float* tm,
   return hipGetLastError();
 }
 
-hipError_t pack_w(const double* w, int np, int rows, int c1, double* wp, double* wm, long ldp, long ldm,
-                  hipStream_t st) {
-  const long n = (long)rows * c1 * (ldp + ldm);
-  hipLaunchKernelGGL((pack_w_kernel<double>), dim3(blocks_for(n)), dim3(kThreads), 0, st, w, np, rows, c1, wp, wm,
+template <typename T>
+static hipError_t launch_pack_w(const T* w, int np, int rows, int c1, T* wp, T* wm, long ldp, long ldm,
+                                hipStream_t st) {
+  const long pairs = (long)rows * c1;
+  if (pairs <= 0 || np <= 0) return hipSuccess;
+  const int nt = (np + kPackTile - 1) / kPackTile;
+  const unsigned gy = (unsigned)std::min<long>(pairs, 65535);
+  hipLaunchKernelGGL((pack_w_kernel<T>), dim3(nt * (nt + 1) / 2, gy), dim3(256), 0, st, w, np, pairs, c1, wp, wm,
                      ldp, ldm);
   return hipGetLastError();
 }
 
+hipError_t pack_w(const double* w, int np, int rows, int c1, double* wp, double* wm, long ldp, long ldm,
+                  hipStream_t st) {
+  return launch_pack_w(w, np, rows, c1, wp, wm, ldp, ldm, st);
+}
+
 hipError_t pack_w_f32(const float* w, int np, int rows, int c1, float* wp, float* wm, long ldp, long ldm,
                       hipStream_t st) {
-  const long n = (long)rows * c1 * (ldp + ldm);
-  hipLaunchKernelGGL((pack_w_kernel<float>), dim3(blocks_for(n)), dim3(kThreads), 0, st, w, np, rows, c1, wp, wm,
-                     ldp, ldm);
-  return hipGetLastError();
+  return launch_pack_w(w, np, rows, c1, wp, wm, ldp, ldm, st);
 }
 
 hipError_t ladder_scatter_pm_add(const double* sp, const double* sm, int nh, int np, int c0, int c1, double* r2,
