@@ -118,9 +118,11 @@ class GNO:
         return out
 
     def operator_apply(self, coeffs: dict, vec, vec_id):
-        """sum over ranks r of sum_{U,L ordered} coeffs[r][U,L] {a^U_L} |vec>.
+        """sum over ranks r of sum_{U,L} coeffs[r][U,L] {a^U_L} |vec>, every index tuple summed.
 
-        coeffs[r] is an array over (nso,)*(2r); rank 0 is a scalar.
+        coeffs[r] is an array over (nso,)*(2r); rank 0 is a scalar.  The strings of one set
+        of indices differ only by the sign of the reordering, so the sum is taken over
+        increasing tuples U, L with the signed sum of the coefficients of their orderings.
         """
         out = np.zeros_like(vec)
         nso = self.F.nso
@@ -128,13 +130,28 @@ class GNO:
             if r == 0:
                 out = out + float(G) * vec
                 continue
-            G = antisymmetrize(G)
-            for U in itertools.combinations(range(nso), r):
-                for L in itertools.combinations(range(nso), r):
-                    c = G[U + L]
-                    if c != 0.0:
-                        out = out + c * self.apply(list(U), list(L), vec, vec_id)
+            combs, Gc = combination_coefficients(G, r, nso)
+            for iu, il in zip(*np.nonzero(Gc)):
+                out = out + Gc[iu, il] * self.apply(list(combs[iu]), list(combs[il]), vec, vec_id)
         return out
+
+
+def combination_coefficients(G, r, nso):
+    """Increasing r-tuples of range(nso) and, for each pair (U, L) of them, the signed sum of
+    G over every reordering of U and of L: the value antisymmetrize(G) takes at (U, L)."""
+    combs = list(itertools.combinations(range(nso), r))
+    idx = np.array(combs, dtype=np.int64).reshape(len(combs), r)
+    perms = list(itertools.permutations(range(r)))
+    out = np.zeros((len(combs), len(combs)))
+    for pu in perms:
+        su = _parity(list(pu))
+        U = idx[:, list(pu)]
+        for pl in perms:
+            sl = _parity(list(pl))
+            L = idx[:, list(pl)]
+            sel = tuple(U[:, None, i] for i in range(r)) + tuple(L[None, :, i] for i in range(r))
+            out += su * sl * G[sel]
+    return combs, out
 
 
 def antisymmetrize(G):
