@@ -99,6 +99,19 @@ int ric_residual(ric_ctx* ctx, const double* T1, const double* T2, double* R1, d
 int ric_update(ric_ctx* ctx, double* T1, double* T2, const double* R1, const double* R2, double s,
                double* step_norm2);
 
+/* Allocation-free variant of ric_update, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Arguments, results, layout and error codes are those of ric_update, computed by the same
+ * kernels.  The only scratch it needs (the 4096 partial sums of the step norm's two-pass
+ * reduction and the result slot) lives in a fixed 64 KiB device array that the library holds
+ * once per GPU from the first ric_create on that GPU until the process ends; the call makes
+ * no device allocation and frees nothing.  Every context on one GPU shares that array and it
+ * keeps the last call's contents (each call overwrites all it reads), so calls that overlap
+ * on one GPU (other threads or streams) race; serialize them.  RIC_E_ARG if the reduction
+ * ever needed more than the array holds. */
+int ric_update_noalloc(ric_ctx* ctx, double* T1, double* T2, const double* R1, const double* R2, double s,
+                       double* step_norm2);
+
 /* Energy (Section 2.2): e_corr (host) = Hbar_0 - E0 with the energy approximation;
  * e0 (host, may be NULL) = <Psi0|H|Psi0>, with h recovered from f (Section 2.1). */
 int ric_energy(ric_ctx* ctx, const double* T1, const double* T2, double* e_corr, double* e0);

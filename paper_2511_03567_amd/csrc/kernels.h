@@ -6,6 +6,10 @@ namespace ric {
 
 constexpr int kMaxDims = 8;
 
+// partial sums of the two-pass reductions (dot products, update and Lagrangian norms): every
+// caller passes a buffer of this many doubles
+constexpr int kReducePartials = 4096;
+
 // Iteration space shared by an output view and an input view: element i of the
 // space (row-major over ext) is out[sum x_d so[d]] and in[sum x_d si[d]].
 struct Iter {
@@ -39,10 +43,10 @@ hipError_t flow_scale(const double* l1, const double* l2, const double* eps, int
 hipError_t flow_fock_gradient(const double* t1, const double* t2, const double* r1, const double* r2,
                               const double* l1, const double* l2, const double* eps, int nc, int na, int nv,
                               double s, double* df, hipStream_t st);
-// out[0] += alpha * sum a[i] b[i] (deterministic two-pass); partial needs 4096 doubles
+// out[0] += alpha * sum a[i] b[i] (deterministic two-pass); partial needs kReducePartials doubles
 hipError_t dot_accumulate(const double* a, const double* b, long n, double alpha, double* out, double* partial,
                           hipStream_t st);
-// regularized update of T1, T2 in place; norm2[0] = ||t_new - t||^2; partial needs 4096 doubles
+// regularized update of T1, T2 in place; norm2[0] = ||t_new - t||^2; partial needs kReducePartials doubles
 hipError_t ric_update_kernel(double* t1, double* t2, const double* r1, const double* r2, const double* eps, int nc,
                              int na, int nv, double s, double* partial, double* norm2, hipStream_t st);
 hipError_t fock_diagonal(const double* f, int n, double* eps, hipStream_t st);

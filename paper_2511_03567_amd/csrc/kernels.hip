@@ -15,7 +15,7 @@ namespace ric {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kRedBlocks = 4096;  // partial sums of the two-pass reductions (callers hold that many doubles)
+constexpr int kRedBlocks = kReducePartials;  // blocks of the two-pass reductions, one partial sum each
 
 inline int blocks_for(long n, int per = kThreads) {
   long b = (n + per - 1) / per;

@@ -15,6 +15,7 @@
 #include <map>
 #include <set>
 #include <memory>
+#include <mutex>
 #include <sstream>
 #include <stdexcept>
 #include <string>
@@ -209,6 +210,32 @@ struct Pool {
 
 }  // namespace
 
+// Device memory of the allocation-free update (ric_update_noalloc): the partial sums of the
+// norm's two-pass reduction followed by the result slot.  One copy per GPU, held from the first
+// context created on that GPU until the process ends, shared by every context there.  Host code
+// never passes `scratch` itself to a kernel (in host code it names a host-side stand-in): it uses
+// the device address hipGetSymbolAddress returns for the current device, kept per device below.
+constexpr size_t kNoAllocDoubles = 8192;   // 64 KiB
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, double*> g_scratch_addr;   // device -> address of that device's copy of `scratch`
+
+// Address of `scratch` on `device`, looked up once per device; the device must be current.
+double* noalloc_scratch(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_addr.find(device);
+  if (it != g_scratch_addr.end()) return it->second;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || p == nullptr)
+    throw Err(RIC_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  g_scratch_addr[device] = static_cast<double*>(p);
+  return static_cast<double*>(p);
+}
+}  // namespace
+
 // fp64 elements of split-K partial tiles (2 GiB)
 constexpr size_t kSplitScratch = 256UL * 1024 * 1024;
 
@@ -236,6 +263,7 @@ struct ric_ctx {
   double ladder_ms = 0.0, total_ms = 0.0;
   bool ladder_ran = false;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  double* noalloc = nullptr;  // this device's copy of `scratch` (set by ric_create)
 
   ~ric_ctx() {
     for (DevBuf* b : {&f, &eps, &B, &BT, &BT32, &g1, &g2, &g3, &ga, &ea, &l2, &k2, &l3, &k3, &I4, &I3, &IJ, &IK,
@@ -551,7 +579,7 @@ struct ric_ctx {
       scrB.ensure(cb ? 0 : K);
       if (ca) pa = a.p; else { gather(a, ka, scrA.p, nullptr); pa = scrA.p; }
       if (cb) pb = b.p; else { gather(b, kb, scrB.p, nullptr); pb = scrB.p; }
-      red.ensure(4096);
+      red.ensure(ric::kReducePartials);
       if (fresh) HIPCHK(ric::fill(out.p, 1, 0.0, stream));
       HIPCHK(ric::dot_accumulate(pa, pb, K, alpha, out.p, red.p, stream));
       return;
@@ -1247,6 +1275,7 @@ int ric_create(ric_ctx** out, int device, void* hip_stream, const char* plan_pat
   ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
   int rc = guard(ctx, [&] {
     for (auto& e : ctx->ev) HIPCHK(hipEventCreate(&e));
+    ctx->noalloc = noalloc_scratch(device);   // guard() made `device` current
     ctx->load_plan(plan_path ? std::string(plan_path) : default_plan_path());
   });
   if (rc != RIC_OK) {
@@ -1403,12 +1432,35 @@ int ric_update(ric_ctx* ctx, double* T1, double* T2, const double* R1, const dou
     ctx->require_loaded();
     if (!T1 || !T2 || !R1 || !R2) throw Err(RIC_E_ARG, "null amplitude/residual pointer");
     if (!(s >= 0.0)) throw Err(RIC_E_ARG, "flow parameter must be >= 0");
-    ctx->red.ensure(4096);
+    ctx->red.ensure(ric::kReducePartials);
     ctx->Edev.ensure(4);
     HIPCHK(ric::ric_update_kernel(T1, T2, R1, R2, ctx->eps.p, ctx->sz.nc, ctx->sz.na, ctx->sz.nv, s, ctx->red.p,
                                   ctx->Edev.p + 1, ctx->stream));
     double v = 0.0;
     HIPCHK(hipMemcpyAsync(&v, ctx->Edev.p + 1, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (!std::isfinite(v)) throw Err(RIC_E_NONFINITE, "non-finite amplitude step");
+    if (step_norm2) *step_norm2 = v;
+  });
+}
+
+int ric_update_noalloc(ric_ctx* ctx, double* T1, double* T2, const double* R1, const double* R2, double s,
+                       double* step_norm2) {
+  return guard(ctx, [&] {
+    ctx->require_loaded();
+    if (!T1 || !T2 || !R1 || !R2) throw Err(RIC_E_ARG, "null amplitude/residual pointer");
+    if (!(s >= 0.0)) throw Err(RIC_E_ARG, "flow parameter must be >= 0");
+    // the same kernels as ric_update, with the reduction's partial sums and result in `scratch`
+    constexpr size_t need = (size_t)ric::kReducePartials + 1;
+    static_assert(need <= kNoAllocDoubles, "reduction partials exceed the allocation-free scratch");
+    if (need > kNoAllocDoubles) throw Err(RIC_E_ARG, "reduction needs more than the allocation-free scratch holds");
+    if (!ctx->noalloc) throw Err(RIC_E_STATE, "allocation-free scratch not set up");
+    double* partial = ctx->noalloc;
+    double* result = ctx->noalloc + ric::kReducePartials;
+    HIPCHK(ric::ric_update_kernel(T1, T2, R1, R2, ctx->eps.p, ctx->sz.nc, ctx->sz.na, ctx->sz.nv, s, partial, result,
+                                  ctx->stream));
+    double v = 0.0;
+    HIPCHK(hipMemcpyAsync(&v, result, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     if (!std::isfinite(v)) throw Err(RIC_E_NONFINITE, "non-finite amplitude step");
     if (step_norm2) *step_norm2 = v;
@@ -1514,7 +1566,7 @@ int ric_lambda_update(ric_ctx* ctx, double* L1, double* L2, const double* G1, co
     ctx->require_loaded();
     if (!L1 || !L2 || !G1 || !G2 || !J1 || !J2) throw Err(RIC_E_ARG, "null pointer");
     if (!(s >= 0.0)) throw Err(RIC_E_ARG, "flow parameter must be >= 0");
-    ctx->red.ensure(4096);
+    ctx->red.ensure(ric::kReducePartials);
     ctx->Edev.ensure(4);
     HIPCHK(ric::lambda_update(L1, L2, G1, G2, J1, J2, ctx->eps.p, ctx->sz.nc, ctx->sz.na, ctx->sz.nv, s, ctx->red.p,
                               ctx->Edev.p + 3, ctx->stream));
@@ -1784,7 +1836,7 @@ int ric_semicanonicalize(ric_ctx* ctx, double* U, double* f_out) {
 int ric_vec_dot(ric_ctx* ctx, const double* a, const double* b, long n, double* out) {
   return guard(ctx, [&] {
     if (!a || !b || !out || n < 0) throw Err(RIC_E_ARG, "bad vector arguments");
-    ctx->red.ensure(4096);
+    ctx->red.ensure(ric::kReducePartials);
     ctx->Edev.ensure(4);
     HIPCHK(ric::fill(ctx->Edev.p, 1, 0.0, ctx->stream));
     HIPCHK(ric::dot_accumulate(a, b, n, 1.0, ctx->Edev.p, ctx->red.p, ctx->stream));

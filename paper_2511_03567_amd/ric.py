@@ -52,6 +52,7 @@ def library():
     lib.ric_load_rdms.argtypes = [P, P, P, P]
     lib.ric_residual.argtypes = [P, P, P, P, P, I]
     lib.ric_update.argtypes = [P, P, P, P, P, D, ctypes.POINTER(D)]
+    lib.ric_update_noalloc.argtypes = [P, P, P, P, P, D, ctypes.POINTER(D)]
     lib.ric_energy.argtypes = [P, P, P, ctypes.POINTER(D), ctypes.POINTER(D)]
     lib.ric_ladder.argtypes = [P, P, P, I]
     lib.ric_last_timings.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(D)]
@@ -67,7 +68,7 @@ def library():
     lib.ric_last_error.argtypes = [P]
     lib.ric_last_error.restype = ctypes.c_char_p
     for fn in ("ric_create", "ric_set_spaces", "ric_load_fock", "ric_load_df", "ric_load_rdms",
-               "ric_residual", "ric_update", "ric_energy", "ric_ladder", "ric_last_timings",
+               "ric_residual", "ric_update", "ric_update_noalloc", "ric_energy", "ric_ladder", "ric_last_timings",
                "ric_adjoint_residual", "ric_energy_gradient", "ric_lambda_update", "ric_flow_scale",
                "ric_flow_fock_gradient", "ric_vec_dot", "ric_vec_axpby", "ric_build_fock",
                "ric_semicanonicalize"):
@@ -156,6 +157,14 @@ class Context:
         out = ctypes.c_double()
         self._check(self.lib.ric_update(self.h, _ptr(T1, s1, "T1"), _ptr(T2, s2, "T2"), _ptr(R1, s1, "R1"),
                                         _ptr(R2, s2, "R2"), float(s), ctypes.byref(out)))
+        return out.value
+
+    def update_noalloc(self, T1, T2, R1, R2, s):
+        """ric_update without any device allocation (scratch in the library's static array)."""
+        s1, s2 = self.amplitude_shapes()
+        out = ctypes.c_double()
+        self._check(self.lib.ric_update_noalloc(self.h, _ptr(T1, s1, "T1"), _ptr(T2, s2, "T2"), _ptr(R1, s1, "R1"),
+                                                _ptr(R2, s2, "R2"), float(s), ctypes.byref(out)))
         return out.value
 
     def energy(self, T1, T2):
