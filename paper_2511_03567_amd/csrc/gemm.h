@@ -1,4 +1,4 @@
-// NT contraction kernels: C[M][N] = alpha * A[M][K] * B[N][K]^T + beta * C (see gemm.hip).
+// Contraction kernels: C[M][N] = alpha * A(M x K) * B(N x K)^T + beta * C (see gemm.hip).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstddef>
@@ -14,6 +14,8 @@ struct GemmArgs {
   int zdiv = 1;           // batch z uses A[z / zdiv], B[z % zdiv], C[z]
   long strideA = 0, strideB = 0, strideC = 0;
   int site = 0;           // 1: particle-particle ladder (a separate kernel symbol for profiles)
+  bool ta = false;        // A stored K-major: element (m, k) at A[k * lda + m] (else A[m * lda + k])
+  bool tb = false;        // B stored K-major: element (n, k) at B[k * ldb + n] (else B[n * ldb + k])
 };
 
 // scratch: fp64 workspace for split-K partial tiles (may be null when scratch_elems == 0)
@@ -24,8 +26,5 @@ hipError_t gemm_nt_f32(const GemmArgs& g, const float* A, const float* B, hipStr
 
 // fp32 operands and fp32 result (fp64 accumulation inside the tile); no split-K
 hipError_t gemm_nt_f32_out32(const GemmArgs& g, const float* A, const float* B, float* C, hipStream_t st);
-
-// select the tile geometry (0: 128x128x16, 1: 128x128x32, 2: 256x128x16, 3: 256x256x16); -1 default
-void gemm_set_variant(int v);
 
 }  // namespace ric

@@ -1,14 +1,20 @@
-// Dense contraction kernels for gfx950 (CDNA4): C[M][N] = alpha * A[M][K] * B[N][K]^T + beta * C.
+// Dense contraction kernels for gfx950 (CDNA4): C[M][N] = alpha * A(M x K) * B(N x K)^T + beta * C.
 //
-// Every binary tensor contraction of the residual is brought to this "NT" form
-// (both operands contiguous along the contracted index K), so one MFMA kernel
-// serves the ring, hole-hole, integral-build and ladder contractions.
+// Every binary tensor contraction of the residual is brought to this form, so one
+// MFMA kernel serves the ring, hole-hole, integral-build and ladder contractions.
+// Each operand is read in the layout it already has in HBM:
+//   A row-major  [M][K] (K contiguous)  or  A "K-major" [K][M] (M contiguous, ta = true),
+//   B row-major  [N][K] (K contiguous)  or  B "K-major" [K][N] (N contiguous, tb = true),
+// so a stored block whose contracted indices lead (the integral blocks, read with
+// their hole-particle pairs summed) needs no transposed copy.
 //
 // Tiling: a 256-thread workgroup (4 wavefronts of 64 lanes, arranged 2 x 2)
 // computes a 128 x 128 tile of C; each wavefront owns 64 x 64 = 4 x 4 MFMA
-// tiles of 16 x 16.  K advances in slabs of 16 staged through LDS, double
-// buffered: the next slab is fetched from HBM into registers while the MFMAs
-// consume the current one.
+// tiles of 16 x 16.  K advances in slabs staged through LDS, double buffered:
+// the next slab is fetched from HBM into registers while the MFMAs consume the
+// current one.  A row-major operand's slab sits in LDS as [row][k] (rows padded by
+// one element); a K-major operand's slab as [k][row] (rows padded by two), both
+// read by the MFMA loop with 16 consecutive lanes on consecutive LDS words.
 //
 // FP64 path: v_mfma_f64_16x16x4f64 (16x16 tile, 4-deep K step).
 // FP32 path (mixed precision): v_mfma_f32_16x16x4f32 on fp32 operands; the
@@ -47,127 +53,149 @@ template <int BM_, int BN_, int BK_, int WM_, int WN_, int MINB_ = 1>
 struct Geo {
   static constexpr int BM = BM_, BN = BN_, BK = BK_, WM = WM_, WN = WN_, MINB = MINB_;
   static constexpr int NT = 64 * WM * WN;
-  static constexpr int LDSK = BK + 1;           // padded LDS row (elements)
-  static constexpr int KPT = BK < 8 ? BK : 8;   // consecutive k per thread per load
-  static constexpr int TPR = BK / KPT;          // threads per row
-  static constexpr int RPP = NT / TPR;          // rows per pass
-  static constexpr int PA = (BM + RPP - 1) / RPP;
-  static constexpr int PB = (BN + RPP - 1) / RPP;
 };
 
-template <typename T, typename Gm>
-struct Slab {
-  T a[Gm::PA][Gm::KPT];
-  T b[Gm::PB][Gm::KPT];
-};
+// How the threads of a workgroup load one operand's R x BK slab and where it sits in LDS.
+//  TR = false: rows of K contiguous.  Each thread loads KPT consecutive k of one row.
+//  TR = true:  K-major ([k][row], rows contiguous).  Each thread loads RPT consecutive rows
+//              of one k.
+template <typename T, int R, int BK, int NT, bool TR>
+struct Tile {
+  static constexpr int VW = 16 / (int)sizeof(T);
+  // row-major source
+  static constexpr int KPT = BK < 8 ? BK : 8;
+  static constexpr int TPR = BK / KPT;            // threads per row
+  static constexpr int RPP = NT / TPR;            // rows per pass
+  static constexpr int PN = (R + RPP - 1) / RPP;  // passes
+  static constexpr int LDSK = BK + 1;
+  // K-major source
+  static constexpr int RPT0 = R * BK / NT;
+  static constexpr int RPT = RPT0 < VW ? VW : RPT0;   // rows per thread
+  static constexpr int TPK = R / RPT;                 // threads per k
+  static constexpr int KPP = NT / TPK;                // k per pass
+  static constexpr int PT = (BK + KPP - 1) / KPP;     // passes
+  static constexpr int LDSR = R + 2;
+  static constexpr int E = TR ? PT * RPT : PN * KPT;  // elements held per thread
+  static constexpr int LDS = TR ? BK * LDSR : R * LDSK;
+  static_assert(!TR || (R % RPT == 0 && RPT % VW == 0), "K-major tile split");
+  static_assert(TR || BK % KPT == 0, "row-major tile split");
 
-// VEC: rows of A/B are 16-byte aligned and K is a multiple of the vector width,
-// so each thread's run of KPT values is fetched with 16-byte loads.
-template <typename T, typename Gm, bool VEC>
-__device__ inline void fetch(const T* __restrict__ A, const T* __restrict__ B, long lda, long ldb, int M, int N,
-                             int K, int m0, int n0, int k0, int tid, Slab<T, Gm>& s) {
-  const int r = tid / Gm::TPR;
-  const int kk = (tid % Gm::TPR) * Gm::KPT;
-  constexpr int VW = 16 / sizeof(T);
+  // Fetch the slab [k0, k0 + BK) of rows [r0, r0 + R) into registers.  VEC: 16-byte loads
+  // (the contiguous extent is a multiple of the vector width and rows are aligned).
+  template <bool VEC>
+  __device__ static inline void fetch(const T* __restrict__ src, long ld, int nrows, int kend, int r0, int k0,
+                                      int tid, T* v) {
+    if constexpr (!TR) {
+      const int r = tid / TPR;
+      const int kk = (tid % TPR) * KPT;
 #pragma unroll
-  for (int p = 0; p < Gm::PA; ++p) {
-    const int row = r + p * Gm::RPP;
-    const int gm = m0 + row;
-    const bool okr = row < Gm::BM && gm < M;
-    if constexpr (VEC) {
+      for (int p = 0; p < PN; ++p) {
+        const int row = r + p * RPP;
+        const int gr = r0 + row;
+        const bool okr = row < R && gr < nrows;
 #pragma unroll
-      for (int j = 0; j < Gm::KPT; j += VW) {
-        const int gk = k0 + kk + j;
-        if (okr && gk < K) {
-          if constexpr (sizeof(T) == 8) {
-            const d2v v = *reinterpret_cast<const d2v*>(A + (long)gm * lda + gk);
-            s.a[p][j] = v[0];
-            s.a[p][j + 1] = v[1];
+        for (int j = 0; j < KPT; j += (VEC ? VW : 1)) {
+          const int gk = k0 + kk + j;
+          if constexpr (VEC) {
+            if (okr && gk < kend) {
+              if constexpr (sizeof(T) == 8) {
+                const d2v x = *reinterpret_cast<const d2v*>(src + (long)gr * ld + gk);
+                v[p * KPT + j] = x[0];
+                v[p * KPT + j + 1] = x[1];
+              } else {
+                const f4v x = *reinterpret_cast<const f4v*>(src + (long)gr * ld + gk);
+                v[p * KPT + j] = x[0]; v[p * KPT + j + 1] = x[1]; v[p * KPT + j + 2] = x[2]; v[p * KPT + j + 3] = x[3];
+              }
+            } else {
+#pragma unroll
+              for (int q = 0; q < VW; ++q) v[p * KPT + j + q] = T(0);
+            }
           } else {
-            const f4v v = *reinterpret_cast<const f4v*>(A + (long)gm * lda + gk);
-            s.a[p][j] = v[0]; s.a[p][j + 1] = v[1]; s.a[p][j + 2] = v[2]; s.a[p][j + 3] = v[3];
+            v[p * KPT + j] = (okr && gk < kend) ? src[(long)gr * ld + gk] : T(0);
           }
-        } else {
-#pragma unroll
-          for (int q = 0; q < VW; ++q) s.a[p][j + q] = T(0);
         }
       }
     } else {
+      const int kr = tid / TPK;
+      const int rr = (tid % TPK) * RPT;
 #pragma unroll
-      for (int j = 0; j < Gm::KPT; ++j) {
-        const int gk = k0 + kk + j;
-        s.a[p][j] = (okr && gk < K) ? A[(long)gm * lda + gk] : T(0);
+      for (int p = 0; p < PT; ++p) {
+        const int k = kr + p * KPP;
+        const int gk = k0 + k;
+        const bool okk = k < BK && gk < kend;
+#pragma unroll
+        for (int j = 0; j < RPT; j += (VEC ? VW : 1)) {
+          const int gr = r0 + rr + j;
+          if constexpr (VEC) {
+            if (okk && gr < nrows) {
+              if constexpr (sizeof(T) == 8) {
+                const d2v x = *reinterpret_cast<const d2v*>(src + (long)gk * ld + gr);
+                v[p * RPT + j] = x[0];
+                v[p * RPT + j + 1] = x[1];
+              } else {
+                const f4v x = *reinterpret_cast<const f4v*>(src + (long)gk * ld + gr);
+                v[p * RPT + j] = x[0]; v[p * RPT + j + 1] = x[1]; v[p * RPT + j + 2] = x[2]; v[p * RPT + j + 3] = x[3];
+              }
+            } else {
+#pragma unroll
+              for (int q = 0; q < VW; ++q) v[p * RPT + j + q] = T(0);
+            }
+          } else {
+            v[p * RPT + j] = (okk && gr < nrows) ? src[(long)gk * ld + gr] : T(0);
+          }
+        }
       }
     }
   }
+
+  __device__ static inline void stash(T* lds, int tid, const T* v) {
+    if constexpr (!TR) {
+      const int r = tid / TPR;
+      const int kk = (tid % TPR) * KPT;
 #pragma unroll
-  for (int p = 0; p < Gm::PB; ++p) {
-    const int row = r + p * Gm::RPP;
-    const int gn = n0 + row;
-    const bool okr = row < Gm::BN && gn < N;
-    if constexpr (VEC) {
+      for (int p = 0; p < PN; ++p) {
+        const int row = r + p * RPP;
+        if (row < R) {
 #pragma unroll
-      for (int j = 0; j < Gm::KPT; j += VW) {
-        const int gk = k0 + kk + j;
-        if (okr && gk < K) {
-          if constexpr (sizeof(T) == 8) {
-            const d2v v = *reinterpret_cast<const d2v*>(B + (long)gn * ldb + gk);
-            s.b[p][j] = v[0];
-            s.b[p][j + 1] = v[1];
-          } else {
-            const f4v v = *reinterpret_cast<const f4v*>(B + (long)gn * ldb + gk);
-            s.b[p][j] = v[0]; s.b[p][j + 1] = v[1]; s.b[p][j + 2] = v[2]; s.b[p][j + 3] = v[3];
-          }
-        } else {
-#pragma unroll
-          for (int q = 0; q < VW; ++q) s.b[p][j + q] = T(0);
+          for (int j = 0; j < KPT; ++j) lds[row * LDSK + kk + j] = v[p * KPT + j];
         }
       }
     } else {
+      const int kr = tid / TPK;
+      const int rr = (tid % TPK) * RPT;
 #pragma unroll
-      for (int j = 0; j < Gm::KPT; ++j) {
-        const int gk = k0 + kk + j;
-        s.b[p][j] = (okr && gk < K) ? B[(long)gn * ldb + gk] : T(0);
+      for (int p = 0; p < PT; ++p) {
+        const int k = kr + p * KPP;
+        if (k < BK) {
+#pragma unroll
+          for (int j = 0; j < RPT; ++j) lds[k * LDSR + rr + j] = v[p * RPT + j];
+        }
       }
     }
   }
-}
 
-template <typename T, typename Gm>
-__device__ inline void stash(T* As, T* Bs, int tid, const Slab<T, Gm>& s) {
-  const int r = tid / Gm::TPR;
-  const int kk = (tid % Gm::TPR) * Gm::KPT;
-#pragma unroll
-  for (int p = 0; p < Gm::PA; ++p) {
-    const int row = r + p * Gm::RPP;
-    if (row < Gm::BM) {
-#pragma unroll
-      for (int j = 0; j < Gm::KPT; ++j) As[row * Gm::LDSK + kk + j] = s.a[p][j];
-    }
+  // element (row, k) of the slab in LDS
+  __device__ static inline T at(const T* lds, int row, int k) {
+    if constexpr (!TR) return lds[row * LDSK + k];
+    else return lds[k * LDSR + row];
   }
-#pragma unroll
-  for (int p = 0; p < Gm::PB; ++p) {
-    const int row = r + p * Gm::RPP;
-    if (row < Gm::BN) {
-#pragma unroll
-      for (int j = 0; j < Gm::KPT; ++j) Bs[row * Gm::LDSK + kk + j] = s.b[p][j];
-    }
-  }
-}
+};
 
 // Tile kernel.  Acc is the MFMA accumulator type; for fp32 operands the
 // per-slab fp32 result is added into fp64 registers (acc64).
 // Site only separates the symbols of call sites that profiles attribute
 // (0: general contractions, 1: particle-particle ladder).
-template <typename T, typename Acc, typename TC, typename Gm, bool VEC, int Site>
+template <typename T, typename Acc, typename TC, typename Gm, bool VEC, bool TA, bool TB, int Site>
 __global__ void __launch_bounds__(Gm::NT, Gm::MINB)
 gemm_nt_kernel(int M, int N, int K, double alpha, const T* __restrict__ A, long lda,
                const T* __restrict__ B, long ldb, double beta, TC* __restrict__ C, long ldc,
                long strideA, long strideB, long strideC, int zdiv, int ksplit, long strideP,
                double* __restrict__ partial) {
-  constexpr int BM = Gm::BM, BN = Gm::BN, BK = Gm::BK, LDSK = Gm::LDSK;
-  __shared__ T As[2][BM * LDSK];
-  __shared__ T Bs[2][BN * LDSK];
+  constexpr int BM = Gm::BM, BN = Gm::BN, BK = Gm::BK, NT = Gm::NT;
+  using TileA = Tile<T, BM, BK, NT, TA>;
+  using TileB = Tile<T, BN, BK, NT, TB>;
+  __shared__ T As[2][TileA::LDS];
+  __shared__ T Bs[2][TileB::LDS];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -206,27 +234,32 @@ gemm_nt_kernel(int M, int N, int K, double alpha, const T* __restrict__ A, long 
       }
     }
 
-  Slab<T, Gm> s;
+  T va[TileA::E], vb[TileB::E];
   int buf = 0;
   if (kbeg < kend) {
-    fetch<T, Gm, VEC>(A, B, lda, ldb, M, N, kend, m0, n0, kbeg, tid, s);
-    stash<T, Gm>(As[0], Bs[0], tid, s);
+    TileA::template fetch<VEC>(A, lda, M, kend, m0, kbeg, tid, va);
+    TileB::template fetch<VEC>(B, ldb, N, kend, n0, kbeg, tid, vb);
+    TileA::stash(As[0], tid, va);
+    TileB::stash(Bs[0], tid, vb);
   }
   __syncthreads();
   const int row = lane & 15;
   const int kq = lane >> 4;
   for (int k0 = kbeg; k0 < kend; k0 += BK) {
     const bool more = k0 + BK < kend;
-    if (more) fetch<T, Gm, VEC>(A, B, lda, ldb, M, N, kend, m0, n0, k0 + BK, tid, s);
+    if (more) {
+      TileA::template fetch<VEC>(A, lda, M, kend, m0, k0 + BK, tid, va);
+      TileB::template fetch<VEC>(B, ldb, N, kend, n0, k0 + BK, tid, vb);
+    }
     const T* as = As[buf];
     const T* bs = Bs[buf];
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       T av[4], bv[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) av[i] = as[(wm + i * 16 + row) * LDSK + kk + kq];
+      for (int i = 0; i < 4; ++i) av[i] = TileA::at(as, wm + i * 16 + row, kk + kq);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bv[j] = bs[(wn + j * 16 + row) * LDSK + kk + kq];
+      for (int j = 0; j < 4; ++j) bv[j] = TileB::at(bs, wn + j * 16 + row, kk + kq);
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -244,7 +277,8 @@ gemm_nt_kernel(int M, int N, int K, double alpha, const T* __restrict__ A, long 
         }
     }
     if (more) {
-      stash<T, Gm>(As[buf ^ 1], Bs[buf ^ 1], tid, s);
+      TileA::stash(As[buf ^ 1], tid, va);
+      TileB::stash(Bs[buf ^ 1], tid, vb);
       buf ^= 1;
     }
     __syncthreads();
@@ -277,8 +311,6 @@ gemm_nt_kernel(int M, int N, int K, double alpha, const T* __restrict__ A, long 
       }
 }
 
-int g_variant = -1;  // -1: default geometry; >= 0 forces one (benchmarking)
-
 // Sum of split-K partial tiles in a fixed order (deterministic), then alpha/beta.
 template <int Site>
 __global__ void splitk_reduce(int M, int N, int ksplit, int batches, double alpha, double beta,
@@ -297,10 +329,25 @@ __global__ void splitk_reduce(int M, int N, int ksplit, int batches, double alph
   }
 }
 
-template <typename T, typename Acc, typename TC, typename Gm, int Site = 0>
+template <typename T, typename Acc, typename TC, typename Gm, int Site, bool TA, bool TB>
+void launch_kernel(bool vec, dim3 grid, hipStream_t st, const GemmArgs& g, const T* A, const T* B, TC* C,
+                   int ksplit, long strideP, double* scratch) {
+  if (vec)
+    hipLaunchKernelGGL((gemm_nt_kernel<T, Acc, TC, Gm, true, TA, TB, Site>), grid, dim3(Gm::NT), 0, st, g.M, g.N, g.K,
+                       g.alpha, A, g.lda, B, g.ldb, g.beta, C, g.ldc, g.strideA, g.strideB, g.strideC, g.zdiv, ksplit,
+                       strideP, scratch);
+  else
+    hipLaunchKernelGGL((gemm_nt_kernel<T, Acc, TC, Gm, false, TA, TB, Site>), grid, dim3(Gm::NT), 0, st, g.M, g.N,
+                       g.K, g.alpha, A, g.lda, B, g.ldb, g.beta, C, g.ldc, g.strideA, g.strideB, g.strideC, g.zdiv,
+                       ksplit, strideP, scratch);
+}
+
+// AllowT: instantiate the K-major operand variants (general contractions only)
+template <typename T, typename Acc, typename TC, typename Gm, int Site = 0, bool AllowT = false>
 hipError_t launch_geo(const GemmArgs& g, const T* A, const T* B, TC* C, hipStream_t st, double* scratch,
                       size_t scratch_elems) {
   constexpr int BM = Gm::BM, BN = Gm::BN;
+  if ((g.ta || g.tb) && !AllowT) return hipErrorInvalidValue;
   const int tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
   // Split K when there are few tiles, choosing the factor so the workgroups fill whole rounds
   // of the resident slots (256 CUs x 2 workgroups of these geometries): the smallest factor
@@ -329,20 +376,24 @@ hipError_t launch_geo(const GemmArgs& g, const T* A, const T* B, TC* C, hipStrea
   }
   while (ksplit > 1 && (long)g.batch * ksplit > 65535) ksplit /= 2;
   if ((long)g.batch * ksplit > 65535) return hipErrorInvalidValue;
+  // 16-byte loads: the contiguous extent of each operand (K for row-major, M or N for
+  // K-major) and its leading dimension are multiples of the vector width, bases aligned
   constexpr int VW = 16 / sizeof(T);
-  const bool vec = (g.K % VW == 0) && (g.lda % VW == 0) && (g.ldb % VW == 0) &&
-                   ((uintptr_t)A % 16 == 0) && ((uintptr_t)B % 16 == 0) && (g.strideA % VW == 0) &&
-                   (g.strideB % VW == 0);
+  const bool va = (g.ta ? g.M % VW == 0 : g.K % VW == 0) && g.lda % VW == 0 && g.strideA % VW == 0 &&
+                  (uintptr_t)A % 16 == 0;
+  const bool vb = (g.tb ? g.N % VW == 0 : g.K % VW == 0) && g.ldb % VW == 0 && g.strideB % VW == 0 &&
+                  (uintptr_t)B % 16 == 0;
+  const bool vec = va && vb;
   dim3 grid(tiles, 1, g.batch * ksplit);
   const long strideP = (long)g.M * g.N;
-  if (vec)
-    hipLaunchKernelGGL((gemm_nt_kernel<T, Acc, TC, Gm, true, Site>), grid, dim3(Gm::NT), 0, st, g.M, g.N, g.K, g.alpha, A,
-                       g.lda, B, g.ldb, g.beta, C, g.ldc, g.strideA, g.strideB, g.strideC, g.zdiv, ksplit, strideP,
-                       scratch);
-  else
-    hipLaunchKernelGGL((gemm_nt_kernel<T, Acc, TC, Gm, false, Site>), grid, dim3(Gm::NT), 0, st, g.M, g.N, g.K, g.alpha, A,
-                       g.lda, B, g.ldb, g.beta, C, g.ldc, g.strideA, g.strideB, g.strideC, g.zdiv, ksplit, strideP,
-                       scratch);
+  if constexpr (AllowT) {
+    if (g.ta && g.tb) launch_kernel<T, Acc, TC, Gm, Site, true, true>(vec, grid, st, g, A, B, C, ksplit, strideP, scratch);
+    else if (g.ta) launch_kernel<T, Acc, TC, Gm, Site, true, false>(vec, grid, st, g, A, B, C, ksplit, strideP, scratch);
+    else if (g.tb) launch_kernel<T, Acc, TC, Gm, Site, false, true>(vec, grid, st, g, A, B, C, ksplit, strideP, scratch);
+    else launch_kernel<T, Acc, TC, Gm, Site, false, false>(vec, grid, st, g, A, B, C, ksplit, strideP, scratch);
+  } else {
+    launch_kernel<T, Acc, TC, Gm, Site, false, false>(vec, grid, st, g, A, B, C, ksplit, strideP, scratch);
+  }
   if (ksplit > 1) {
     const long total = (long)g.batch * g.M * g.N;
     const int nb = (int)std::min<long>((total + 255) / 256, 65536);
@@ -352,12 +403,10 @@ hipError_t launch_geo(const GemmArgs& g, const T* A, const T* B, TC* C, hipStrea
   return hipGetLastError();
 }
 
-using G128x16 = Geo<128, 128, 16, 2, 2>;
-using G128x32 = Geo<128, 128, 32, 2, 2>;
-using G256x16 = Geo<256, 128, 16, 4, 2>;
-using G256sq = Geo<256, 256, 16, 4, 4>;
-using G128x16b2 = Geo<128, 128, 16, 2, 2, 2>;
-using G128x32b2 = Geo<128, 128, 32, 2, 2, 2>;
+// measured on gfx950: fp64 best with 128x128x16 tiles at two workgroups per CU, fp32 with
+// 128x128x32 tiles
+using GeoF64 = Geo<128, 128, 16, 2, 2, 2>;
+using GeoF32 = Geo<128, 128, 32, 2, 2>;
 
 template <typename T, typename Acc, typename TC>
 hipError_t launch(const GemmArgs& g, const T* A, const T* B, TC* C, hipStream_t st, double* scratch,
@@ -365,21 +414,12 @@ hipError_t launch(const GemmArgs& g, const T* A, const T* B, TC* C, hipStream_t 
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
   if (g.K <= 0 && g.beta == 1.0) return hipSuccess;
   if (g.site == 1) {
-    // the ladder's products always take the default tile shape of their type
-    if constexpr (sizeof(T) == 8) return launch_geo<T, Acc, TC, G128x16b2, 1>(g, A, B, C, st, scratch, scratch_elems);
-    else return launch_geo<T, Acc, TC, G128x32, 1>(g, A, B, C, st, scratch, scratch_elems);
+    // the ladder's products: row-major operands, the default tile shape of their type
+    if constexpr (sizeof(T) == 8) return launch_geo<T, Acc, TC, GeoF64, 1>(g, A, B, C, st, scratch, scratch_elems);
+    else return launch_geo<T, Acc, TC, GeoF32, 1>(g, A, B, C, st, scratch, scratch_elems);
   }
-  int v = g_variant;
-  // measured on gfx950: fp64 best with 128x128x16 tiles at two workgroups per CU,
-  // fp32 with 128x128x32 tiles
-  if (v < 0) v = sizeof(T) == 8 ? 3 : 1;
-  switch (v) {
-    case 1: return launch_geo<T, Acc, TC, G128x32>(g, A, B, C, st, scratch, scratch_elems);
-    case 2: return launch_geo<T, Acc, TC, G256x16>(g, A, B, C, st, scratch, scratch_elems);
-    case 3: return launch_geo<T, Acc, TC, G128x16b2>(g, A, B, C, st, scratch, scratch_elems);
-    case 4: return launch_geo<T, Acc, TC, G128x32b2>(g, A, B, C, st, scratch, scratch_elems);
-    default: return launch_geo<T, Acc, TC, G128x16>(g, A, B, C, st, scratch, scratch_elems);
-  }
+  if constexpr (sizeof(T) == 8) return launch_geo<T, Acc, TC, GeoF64, 0, true>(g, A, B, C, st, scratch, scratch_elems);
+  else return launch_geo<T, Acc, TC, GeoF32, 0, sizeof(TC) == 8>(g, A, B, C, st, scratch, scratch_elems);
 }
 
 }  // namespace
@@ -397,7 +437,5 @@ hipError_t gemm_nt_f32(const GemmArgs& g, const float* A, const float* B, hipStr
 hipError_t gemm_nt_f32_out32(const GemmArgs& g, const float* A, const float* B, float* C, hipStream_t st) {
   return launch<float, f4, float>(g, A, B, C, st, nullptr, 0);
 }
-
-void gemm_set_variant(int v) { g_variant = v; }
 
 }  // namespace ric

@@ -7,6 +7,7 @@
 //  * deterministic two-pass reductions (energy dot products, norms);
 //  * density-cumulant preparation (Section 2.1 and 2.3.2) and the reference energy.
 #include <hip/hip_runtime.h>
+#include <algorithm>
 #include <cstdint>
 #include "kernels.h"
 
@@ -54,22 +55,47 @@ __global__ void fill_kernel(double* __restrict__ p, long n, double v) {
   for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) p[t] = v;
 }
 
-// X[k,l,c,d] <- X[k,l,c,d] + X[l,k,d,c]; each pair handled by its lower index
-__global__ void symmetrize_kernel(double* __restrict__ x, int nh, int np, double scale) {
-  const long total = (long)nh * nh * np * np;
-  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
-    const int d = (int)(t % np);
-    const int c = (int)((t / np) % np);
-    const int l = (int)((t / ((long)np * np)) % nh);
-    const int k = (int)(t / ((long)np * np * nh));
-    const long u = (((long)l * nh + k) * np + d) * np + c;
-    if (t < u) {
-      const double s = scale * (x[t] + x[u]);
-      x[t] = s;
-      x[u] = s;
-    } else if (t == u) {
-      x[t] = 2.0 * scale * x[t];
-    }
+// X[k,l,c,d] <- scale (X[k,l,c,d] + X[l,k,d,c]) over [nh][nh][np][np].  One workgroup takes a
+// hole pair k <= l (grid.y) and a 32 x 32 tile (C, D) of the particle pairs (grid.x): it reads
+// the tile of the (k, l) matrix and the mirrored tile (D, C) of the (l, k) matrix with
+// row-contiguous loads, transposes the mirror through LDS, and writes the symmetrized values
+// to both places.  For k == l only the tiles C <= D run (they cover the mirror as well).
+constexpr int kSymTile = 32;
+
+__global__ void __launch_bounds__(256) symmetrize_kernel(double* __restrict__ x, int nh, int np, double scale) {
+  constexpr int TS = kSymTile;
+  __shared__ double a[TS][TS + 1];
+  __shared__ double b[TS][TS + 1];
+  const int nt = (np + TS - 1) / TS;
+  const int CB = blockIdx.x / nt, DB = blockIdx.x % nt;
+  const long pairs = (long)nh * (nh + 1) / 2;
+  const long pp = (long)np * np;
+  // hole pairs k <= l by the packed index pr = l (l + 1) / 2 + k; the loop bounds and the skip
+  // are uniform over the workgroup, so its barriers are reached by every thread
+  for (long pr = blockIdx.y; pr < pairs; pr += gridDim.y) {
+  int l = (int)((sqrt(8.0 * pr + 1.0) - 1.0) / 2.0);
+  while ((long)l * (l + 1) / 2 > pr) --l;
+  while ((long)(l + 1) * (l + 2) / 2 <= pr) ++l;
+  const int k = (int)(pr - (long)l * (l + 1) / 2);
+  if (k == l && CB > DB) continue;
+  double* xkl = x + ((long)k * nh + l) * pp;
+  double* xlk = x + ((long)l * nh + k) * pp;
+  const int tx = threadIdx.x % TS, ty = threadIdx.x / TS;
+  constexpr int RPP = 256 / TS;
+  for (int i = ty; i < TS; i += RPP) {
+    const int c = CB * TS + i, d = DB * TS + tx;
+    a[i][tx] = (c < np && d < np) ? xkl[(long)c * np + d] : 0.0;       // X[k,l,c,d]
+    const int d2 = DB * TS + i, c2 = CB * TS + tx;
+    b[i][tx] = (d2 < np && c2 < np) ? xlk[(long)d2 * np + c2] : 0.0;    // X[l,k,d2,c2]
+  }
+  __syncthreads();
+  for (int i = ty; i < TS; i += RPP) {
+    const int c = CB * TS + i, d = DB * TS + tx;
+    if (c < np && d < np) xkl[(long)c * np + d] = scale * (a[i][tx] + b[tx][i]);
+    const int d2 = DB * TS + i, c2 = CB * TS + tx;
+    if (d2 < np && c2 < np) xlk[(long)d2 * np + c2] = scale * (b[i][tx] + a[tx][i]);
+  }
+  __syncthreads();   // the next pair overwrites the tiles
   }
 }
 
@@ -153,37 +179,49 @@ __device__ inline double phi(double D, double s) {
   return -expm1(-s * D * D) / D;
 }
 
+// Rows of the amplitude arrays: T1 row k (np elements) and T2 row (k, l, c) (np elements over d).
+// Each workgroup takes a contiguous range of rows; the hole part of Delta and the mask are
+// per row, so the inner loop is a coalesced stream over d with no index arithmetic.
 __global__ void __launch_bounds__(kThreads)
 update_kernel(double* __restrict__ t1, double* __restrict__ t2, const double* __restrict__ r1,
               const double* __restrict__ r2, const double* __restrict__ eps, int nc, int na, int nv,
               double s, double* __restrict__ partial) {
   const int nh = nc + na, np = na + nv;
-  const long n1 = (long)nh * np;
-  const long n2 = (long)nh * nh * np * np;
-  const long total = n1 + n2;
-  const long per = (total + gridDim.x - 1) / gridDim.x;
+  const long rows = (long)nh + (long)nh * nh * np;
+  const long per = (rows + gridDim.x - 1) / gridDim.x;
   const long beg = blockIdx.x * per;
-  const long end = beg + per < total ? beg + per : total;
+  const long end = beg + per < rows ? beg + per : rows;
+  const double* epsP = eps + nc;
   double acc = 0.0;
-  for (long t = beg + threadIdx.x; t < end; t += blockDim.x) {
-    if (t < n1) {
-      const int k = (int)(t / np), c = (int)(t % np);
-      if (k >= nc && c < na) continue;
-      const double D = eps[k] - eps[nc + c];
-      const double nw = (t1[t] * D + r1[t]) * phi(D, s);
-      const double dv = nw - t1[t];
-      acc += dv * dv;
-      t1[t] = nw;
+  for (long r = beg; r < end; ++r) {
+    double* t;
+    const double* q;
+    double Dh;
+    bool masked;
+    if (r < nh) {
+      const int k = (int)r;
+      t = t1 + (long)k * np;
+      q = r1 + (long)k * np;
+      Dh = eps[k];
+      masked = k >= nc;                  // T1 active -> active left out
     } else {
-      const long u = t - n1;
-      int k, l, c, d;
-      amp2_index(u, nh, np, k, l, c, d);
-      if (k >= nc && l >= nc && c < na && d < na) continue;
-      const double D = eps[k] + eps[l] - eps[nc + c] - eps[nc + d];
-      const double nw = (t2[u] * D + r2[u]) * phi(D, s);
-      const double dv = nw - t2[u];
+      const long u = r - nh;             // (k, l, c)
+      const int c = (int)(u % np);
+      const long kl = u / np;
+      const int l = (int)(kl % nh), k = (int)(kl / nh);
+      t = t2 + u * np;
+      q = r2 + u * np;
+      Dh = eps[k] + eps[l] - epsP[c];
+      masked = k >= nc && l >= nc && c < na;   // T2 all-active left out
+    }
+    const int dmin = masked ? na : 0;    // the excluded all-active elements lead the row
+    for (int d = dmin + threadIdx.x; d < np; d += blockDim.x) {
+      const double D = Dh - epsP[d];
+      const double tv = t[d];
+      const double nw = (tv * D + q[d]) * phi(D, s);
+      const double dv = nw - tv;
       acc += dv * dv;
-      t2[u] = nw;
+      t[d] = nw;
     }
   }
   acc = block_sum(acc);
@@ -641,18 +679,17 @@ hipError_t fill(double* p, long n, double v, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t symmetrize_pairs(double* x, int nh, int np, hipStream_t st) {
-  const long n = (long)nh * nh * np * np;
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(symmetrize_kernel, dim3(blocks_for(n)), dim3(kThreads), 0, st, x, nh, np, 1.0);
+hipError_t symmetrize_pairs_scaled(double* x, int nh, int np, double scale, hipStream_t st) {
+  if (nh <= 0 || np <= 0) return hipSuccess;
+  const int nt = (np + kSymTile - 1) / kSymTile;
+  const long pairs = (long)nh * (nh + 1) / 2;
+  hipLaunchKernelGGL(symmetrize_kernel, dim3(nt * nt, (unsigned)std::min<long>(pairs, 65535)), dim3(256), 0, st, x,
+                     nh, np, scale);
   return hipGetLastError();
 }
 
-hipError_t symmetrize_pairs_scaled(double* x, int nh, int np, double scale, hipStream_t st) {
-  const long n = (long)nh * nh * np * np;
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(symmetrize_kernel, dim3(blocks_for(n)), dim3(kThreads), 0, st, x, nh, np, scale);
-  return hipGetLastError();
+hipError_t symmetrize_pairs(double* x, int nh, int np, hipStream_t st) {
+  return symmetrize_pairs_scaled(x, nh, np, 1.0, st);
 }
 
 hipError_t lambda_update(double* l1, double* l2, const double* g1, const double* g2, const double* j1,

@@ -529,7 +529,23 @@ struct ric_ctx {
   double fp32_min_flops = getenv("RIC_FP32_MIN_FLOPS") ? std::atof(getenv("RIC_FP32_MIN_FLOPS")) : 1e10;
 
   // -- contraction out (+)= alpha * sum a * b -------------------------------------------------
-  void contract(const View& out, double alpha, const View& a, const View& b, bool fresh, bool allow32) {
+  void contract(const View& out, double alpha, const View& a0, const View& b0, bool fresh, bool allow32) {
+    // C = A B^T is written row by row: the operand carrying the output's innermost index takes
+    // the role of B, so the product lands in the output's own layout
+    const View* pa = &a0;
+    const View* pb = &b0;
+    {
+      int inner = -1;
+      long best = -1;
+      for (int i = 0; i < out.nd; ++i)
+        if (out.ext[i] > 1 && (best < 0 || out.str[i] < best)) {
+          best = out.str[i];
+          inner = i;
+        }
+      if (inner >= 0 && a0.find(out.lab[inner]) >= 0 && b0.find(out.lab[inner]) < 0) std::swap(pa, pb);
+    }
+    const View& a = *pa;
+    const View& b = *pb;
     std::vector<int> aM, aK, bN, bK, oM, oN;
     for (int i = 0; i < out.nd; ++i) {
       const int l = out.lab[i];
@@ -596,6 +612,24 @@ struct ric_ctx {
     if (directB && N > 1 && sBn < K) directB = false;
     if (M == 1) sAm = K;
     if (N == 1) sBn = K;
+    // otherwise an operand whose M (N) indices are contiguous and K indices strided is read
+    // K-major in place
+    bool tA = false, tB = false;
+    long tldA = 0, tldB = 0;
+    if (!use32 && !directA && M > 1 && K > 1) {
+      long sm, sk;
+      if (mergeable(a, aM, sm) && sm == 1 && mergeable(a, aK, sk) && sk >= M) {
+        tA = true;
+        tldA = sk;
+      }
+    }
+    if (!use32 && !directB && N > 1 && K > 1) {
+      long sn, sk;
+      if (mergeable(b, bN, sn) && sn == 1 && mergeable(b, bK, sk) && sk >= N) {
+        tB = true;
+        tldB = sk;
+      }
+    }
     // output as [M][N]
     long sOm, sOn;
     bool directC = mergeable(out, oM, sOm) && mergeable(out, oN, sOn) && (sOn == 1 || N == 1);
@@ -609,23 +643,33 @@ struct ric_ctx {
     long Kp = K;
     if (K % vw != 0 && flops > pad_min_flops && !aK.empty()) {
       Kp = (K + vw - 1) / vw * vw;
-      directA = directB = false;
+      directA = directB = tA = tB = false;
     }
-    if (!directA) scrA.ensure(use32 ? ((size_t)M * Kp + 1) / 2 : (size_t)M * Kp);
-    if (!directB) scrB.ensure(use32 ? ((size_t)N * Kp + 1) / 2 : (size_t)N * Kp);
+    // large products keep 16-byte loads: a K-major operand needs its contiguous extent and
+    // leading dimension in whole vectors, else it is gathered
+    if (flops > pad_min_flops) {
+      if (tA && (M % vw != 0 || tldA % vw != 0)) tA = false;
+      if (tB && (N % vw != 0 || tldB % vw != 0)) tB = false;
+    }
+    if (!directA && !tA) scrA.ensure(use32 ? ((size_t)M * Kp + 1) / 2 : (size_t)M * Kp);
+    if (!directB && !tB) scrB.ensure(use32 ? ((size_t)N * Kp + 1) / 2 : (size_t)N * Kp);
     const double* pA = a.p;
     const double* pB = b.p;
-    if (!directA) {
+    if (tA) sAm = tldA;
+    if (tB) sBn = tldB;
+    if (!directA && !tA) {
       gather(a, ordA, use32 ? nullptr : scrA.p, use32 ? reinterpret_cast<float*>(scrA.p) : nullptr, aK.size(), Kp);
       pA = scrA.p;
       sAm = Kp;
     }
-    if (!directB) {
+    if (!directB && !tB) {
       gather(b, ordB, use32 ? nullptr : scrB.p, use32 ? reinterpret_cast<float*>(scrB.p) : nullptr, bK.size(), Kp);
       pB = scrB.p;
       sBn = Kp;
     }
     GemmArgs g;
+    g.ta = tA;
+    g.tb = tB;
     g.M = (int)M;
     g.N = (int)N;
     g.K = (int)Kp;

@@ -602,15 +602,32 @@ def _chunk_role(members, ylabs0, ext0, g0, ren0):
     return None if best is None else best[0]
 
 
+_VALID = (C, A, V, H, P, G, X)
+
+
+def _tight_ranges(members):
+    """Per label role of a group, the union of the ranges its members use: the accumulator,
+    the stored operand's summed labels and the outputs carried by the accumulator span only
+    the sub-blocks some member writes (instead of the whole hole or particle range)."""
+    tight = {}
+    for m in members:
+        rngm, renm = m[7], m[8]
+        for l, role in renm.items():
+            tight[role] = tight.get(role, 0) | rngm[l]
+    return tight
+
+
 def _emit_groups(plan, groups):
     for key, members in groups.items():
         target = key[0]
-        coef0, ysteps0, Yop0, ylabs0, P00, ext0, out_ranges0, rng0, ren0, g0 = members[0]
+        coef0, ysteps0, Yop0, ylabs0, P00, ext0, out_ranges0, rng0, ren0, g0w = members[0]
         if len(members) == 1 and not ysteps0:
             # plain product of two stored tensors
             out = Operand(target, out_ranges0, ext0)
             plan.contract(out, coef0, P00, Yop0)
             continue
+        tight = _tight_ranges(members)
+        g0 = {l: (tight[ren0[l]] if l in ren0 and tight.get(ren0[l]) in _VALID else r) for l, r in g0w.items()}
         # an accumulator too large to hold whole is built and consumed in chunks of an
         # output label that every member covers over the same range (leading dimension)
         chunk = None
@@ -668,7 +685,13 @@ def _emit_groups(plan, groups):
                 continue
             coef0_, X0, Z0, zl0, rng0_, yl0, m0, _ = items[0]
             yl0 = order(yl0, m0[8])
-            zr = [_widen(rng0_[l]) for l in zl0]
+            # Z's ranges: the union of the items' own ranges, position by position
+            zt = [0] * len(zl0)
+            for it in items:
+                for i, l in enumerate(it[3]):
+                    zt[i] |= it[4][l]
+            zr = [r if r in _VALID else _widen(rng0_[l]) for r, l in zip(zt, zl0)]
+            zpos = {l: i for i, l in enumerate(zl0)}
             zacc = plan.new_tmp(zr)
             plan.lines.append(f"ZERO {zacc}")
             for coef, X, Z, zlabs, rng, ylabs, m, prefix in items:
@@ -677,10 +700,10 @@ def _emit_groups(plan, groups):
                     _emit_steps(plan, prefix, final_out=zop, alpha=coef)
                 else:
                     plan.add(zop, coef, Z)
-            # X over the ranges of the first member, its inner labels widened like Z
-            xr = [(_widen(r) if (l in zl0 and l not in yl0) else r) for l, r in zip(X0.labels, X0.ranges)]
+            # X over the ranges of the first member, its inner labels over Z's ranges
+            xr = [(zr[zpos[l]] if (l in zl0 and l not in yl0) else r) for l, r in zip(X0.labels, X0.ranges)]
             Xop = Operand(X0.name, xr, X0.labels)
-            accop = Operand(acc, [(rng0_[l] if l in X0.labels else _widen(rng0_[l])) for l in yl0], yl0)
+            accop = Operand(acc, [(rng0_[l] if l in X0.labels else zr[zpos[l]]) for l in yl0], yl0)
             plan.contract(accop, 1, Xop, Operand(zacc, zr, zl0))
             plan.free(zacc)
         for coef, ysteps, Yop, ylabs, P0m, ext, out_ranges, rng, ren, g in rest_members:
