@@ -9,8 +9,10 @@
 // their hole-particle pairs summed) needs no transposed copy.
 //
 // Tiling: a 256-thread workgroup (4 wavefronts of 64 lanes, arranged 2 x 2)
-// computes a 128 x 128 tile of C; each wavefront owns 64 x 64 = 4 x 4 MFMA
-// tiles of 16 x 16.  K advances in slabs staged through LDS, double buffered:
+// computes a tile of C: 128 x 128 in fp64 (each wavefront 64 x 64 = 4 x 4 MFMA tiles of
+// 16 x 16, two workgroups per CU), 64 x 128 in fp32 (each wavefront 32 x 64, so the fp64 carry
+// of the fp32 partial sums fits three wavefronts per SIMD).  K advances in slabs staged through
+// LDS, double buffered:
 // the next slab is fetched from HBM into registers while the MFMAs consume the
 // current one.  A row-major operand's slab sits in LDS as [row][k] (rows padded by
 // one element); a K-major operand's slab as [k][row] (rows padded by two), both
@@ -47,12 +49,13 @@ __device__ inline void mma(f4& c, float a, float b) {
   c = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// Geometry of one kernel instance: BM x BN tile, K slab BK, WM x WN wavefronts of
-// 64 x 64 (4 x 4 MFMA tiles of 16 x 16 each).
-template <int BM_, int BN_, int BK_, int WM_, int WN_, int MINB_ = 1>
+// Geometry of one kernel instance: BM x BN tile, K slab BK, WM x WN wavefronts, each owning
+// TI x TJ MFMA tiles of 16 x 16.
+template <int BM_, int BN_, int BK_, int WM_, int WN_, int MINB_ = 1, int TI_ = 4, int TJ_ = 4>
 struct Geo {
-  static constexpr int BM = BM_, BN = BN_, BK = BK_, WM = WM_, WN = WN_, MINB = MINB_;
+  static constexpr int BM = BM_, BN = BN_, BK = BK_, WM = WM_, WN = WN_, MINB = MINB_, TI = TI_, TJ = TJ_;
   static constexpr int NT = 64 * WM * WN;
+  static_assert(BM == WM * 16 * TI && BN == WN * 16 * TJ, "wave tiles");
 };
 
 // How the threads of a workgroup load one operand's R x BK slab and where it sits in LDS.
@@ -199,8 +202,9 @@ gemm_nt_kernel(int M, int N, int K, double alpha, const T* __restrict__ A, long 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wm = (wave / Gm::WN) * 64;
-  const int wn = (wave % Gm::WN) * 64;
+  constexpr int TI = Gm::TI, TJ = Gm::TJ;
+  const int wm = (wave / Gm::WN) * (16 * TI);
+  const int wn = (wave % Gm::WN) * (16 * TJ);
   // batch: z -> (z / zdiv) selects A, (z % zdiv) selects B, z selects C
   const int zb = blockIdx.z / ksplit;
   const int ks = blockIdx.z % ksplit;
@@ -221,12 +225,12 @@ gemm_nt_kernel(int M, int N, int K, double alpha, const T* __restrict__ A, long 
   const int kend = min(K, kbeg + kchunk);
 
   constexpr bool kMixed = sizeof(T) == 4;
-  Acc acc[4][4];
-  double acc64[kMixed ? 4 : 1][4][4];
+  Acc acc[TI][TJ];
+  double acc64[kMixed ? TI : 1][TJ][4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < TI; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < TJ; ++j) {
       acc[i][j] = Acc{0, 0, 0, 0};
       if constexpr (kMixed) {
 #pragma unroll
@@ -255,22 +259,22 @@ gemm_nt_kernel(int M, int N, int K, double alpha, const T* __restrict__ A, long 
     const T* bs = Bs[buf];
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
-      T av[4], bv[4];
+      T av[TI], bv[TJ];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) av[i] = TileA::at(as, wm + i * 16 + row, kk + kq);
+      for (int i = 0; i < TI; ++i) av[i] = TileA::at(as, wm + i * 16 + row, kk + kq);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bv[j] = TileB::at(bs, wn + j * 16 + row, kk + kq);
+      for (int j = 0; j < TJ; ++j) bv[j] = TileB::at(bs, wn + j * 16 + row, kk + kq);
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < TI; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) mma(acc[i][j], av[i], bv[j]);
+        for (int j = 0; j < TJ; ++j) mma(acc[i][j], av[i], bv[j]);
     }
     if constexpr (kMixed) {
       // carry the slab's fp32 partial sums in fp64
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < TI; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < TJ; ++j) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) acc64[i][j][r] += (double)acc[i][j][r];
           acc[i][j] = Acc{0, 0, 0, 0};
@@ -290,9 +294,9 @@ gemm_nt_kernel(int M, int N, int K, double alpha, const T* __restrict__ A, long 
   const int rstep = kMixed ? 1 : 4;
   const long ldo = ksplit > 1 ? (long)N : ldc;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < TI; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < TJ; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int gm = m0 + wm + i * 16 + crow + r * rstep;
@@ -403,10 +407,11 @@ hipError_t launch_geo(const GemmArgs& g, const T* A, const T* B, TC* C, hipStrea
   return hipGetLastError();
 }
 
-// measured on gfx950: fp64 best with 128x128x16 tiles at two workgroups per CU, fp32 with
-// 128x128x32 tiles
+// measured on gfx950 (ring, ladder and square shapes): fp64 best with 128x128x16 tiles at two
+// workgroups per CU (64x128 and 128x64 tiles at three were 1-7 % slower); fp32 with fp64 carry
+// best with 64x128x32 tiles at up to three workgroups per CU (8-20 % over 128x128x32 at one)
 using GeoF64 = Geo<128, 128, 16, 2, 2, 2>;
-using GeoF32 = Geo<128, 128, 32, 2, 2>;
+using GeoF32 = Geo<64, 128, 32, 2, 2, 2, 2, 4>;
 
 template <typename T, typename Acc, typename TC>
 hipError_t launch(const GemmArgs& g, const T* A, const T* B, TC* C, hipStream_t st, double* scratch,
