@@ -61,6 +61,36 @@ enum {
 
 enum { RIC_FP64 = 0, RIC_FP32MIX = 1 };
 
+/* Term groups of the residual (ric_residual's term_mask), so each part can be checked on its own:
+ * a mask selects at least one of LINEAR / QUADRATIC and at least one of LADDER / NONLADDER. */
+enum {
+  RIC_TERMS_LINEAR = 1,      /* H + [H,T] (Section 2.2) */
+  RIC_TERMS_QUADRATIC = 2,   /* 1/2 [[H,T],T] with the approximations of Section 2.2 */
+  RIC_TERMS_LADDER = 4,      /* the particle-particle ladder sum_{ef} (ce|df) tau[k,l,e,f] of those groups */
+  RIC_TERMS_NONLADDER = 8,   /* every other term of those groups */
+  RIC_TERMS_ALL = 15
+};
+
+/* One amplitude class of Section 3.2 as a sub-block of the dense layout below: dimension i
+ * covers [start[i], start[i] + extent[i]) of its range (holes H = core + active in [0, nH),
+ * particles P = active + virtual in [0, nP)). */
+typedef struct {
+  char name[8];     /* "IA", "IT", "TA" (singles); "IJAB", "IJTU", "TUAB", "ITAB", "ITUV", "IJTA", "TUVA",
+                       "ITUA1" (T[i,t,u,a] = t^{ua}_{it}), "ITUA2" (T[i,t,a,u] = t^{au}_{it}) (doubles) */
+  int rank;         /* 1: block of T1[nH][nP]; 2: block of T2[nH][nH][nP][nP] */
+  int start[4];
+  int extent[4];    /* unused dimensions 0 */
+} ric_block_t;
+
+typedef struct {
+  int nc, na, nv, naux, nh, np;
+  long t1_elems;    /* nH * nP: length of T1, R1 (and of every singles-shaped argument) */
+  long t2_elems;    /* nH * nH * nP * nP: length of T2, R2 */
+  int nblocks;      /* 12: the 3 singles and 9 doubles classes.  Every other doubles sub-block is the pair
+                       image T2[l][k][d][c] of one of them (kept equal) or the excluded all-active block */
+  ric_block_t block[12];
+} ric_layout_t;
+
 /* Create a context on `device` using `hip_stream` (a hipStream_t, may be NULL).
  * plan_path: the contraction plan generated from the paper's equations
  * (plan.txt shipped next to the library); NULL selects that default file.
@@ -76,9 +106,15 @@ int ric_set_spaces(ric_ctx* ctx, int nc, int na, int nv, int naux);
  * Its diagonal gives the denominators Delta of eq. cc-update. */
 int ric_load_fock(ric_ctx* ctx, const double* f);
 
-/* Density-fitting factors B[P][p][q], naux x n x n row-major, symmetric in (p,q);
- * copied.  Builds the stored integral blocks with at most two particle indices. */
-int ric_load_df(ric_ctx* ctx, const double* B);
+/* Where each amplitude class of Section 3.2 sits in the T1/T2 arrays (host output), for the
+ * spaces set by ric_set_spaces. */
+int ric_layout(const ric_ctx* ctx, ric_layout_t* out);
+
+/* Density-fitting factors B[P][p][q], naux x n x n row-major, symmetric in (p,q).
+ * borrow = 0: copied.  borrow = 1: the caller's device array is used in place (no second copy, 11.5 GB
+ * at 809 orbitals); it must stay alive and unchanged until the next ric_load_df, ric_set_spaces or
+ * ric_destroy.  Builds the stored integral blocks with at most two particle indices. */
+int ric_load_df(ric_ctx* ctx, const double* B, int borrow);
 
 /* Spin-free RDMs of the active space (Section 2.3.2): G1[t][u] = Gamma^t_u,
  * G2[t][u][v][w] = Gamma^{tu}_{vw}, G3[t][u][v][w][x][y] = Gamma^{tuv}_{wxy}
@@ -89,8 +125,11 @@ int ric_load_rdms(ric_ctx* ctx, const double* G1, const double* G2, const double
 /* Many-body residuals (Section 2.2) of the amplitudes T1, T2 (layout above):
  * R1 = r^c_k (alpha), R2 = r^{c dbar}_{k lbar}.  precision: RIC_FP64, or
  * RIC_FP32MIX (large contractions with fp32 MFMA operands and fp64 accumulation;
- * cumulant, energy and update work stays fp64).  R1, R2 are overwritten. */
-int ric_residual(ric_ctx* ctx, const double* T1, const double* T2, double* R1, double* R2, int precision);
+ * cumulant, energy and update work stays fp64).  term_mask (RIC_TERMS_*): the term groups
+ * evaluated, RIC_TERMS_ALL for the residual itself.  R1, R2 are overwritten (the excluded
+ * blocks zero, R2 pair-symmetric in every case). */
+int ric_residual(ric_ctx* ctx, const double* T1, const double* T2, double* R1, double* R2, int precision,
+                 unsigned term_mask);
 
 /* Flow-regularized Jacobi update (eq. ric-update), in place:
  * t <- (t Delta + r) (1 - exp(-s Delta^2)) / Delta, Delta = sum of hole minus
@@ -140,9 +179,10 @@ int ric_ladder(ric_ctx* ctx, const double* tau, double* R2, int precision);
  * dF and dB are not NULL, dF = (dr/df)^T x (n x n), dB = (dr/dB)^T x (naux x n x n).
  * The particle-particle ladder is transposed by rebuilding (ce|df) from B in chunks (for dT)
  * and by forming sum_kl x[k,l,c,d] tau[k,l,e,f] in chunks of c (for dB); neither is stored.
- * All outputs are overwritten.  FP64. */
+ * dT is overwritten; dF and dB are overwritten (accumulate = 0) or added to (accumulate = 1,
+ * e.g. onto the energy gradient).  FP64. */
 int ric_adjoint_residual(ric_ctx* ctx, const double* T1, const double* T2, const double* X1, const double* X2,
-                         double* dT1, double* dT2, double* dF, double* dB);
+                         double* dT1, double* dT2, double* dF, double* dB, int accumulate);
 
 /* Gradient of the correlation energy functional of Section 2.2 at fixed amplitudes:
  * dT = dE/dT, dF = dE/df, dB = dE/dB.  Outputs overwritten.  FP64. */
@@ -176,7 +216,8 @@ int ric_build_fock(ric_ctx* ctx, const double* h, double* f);
  * blocks of the loaded f (rocSOLVER dsyevd on the device), and replaces the loaded f, DF
  * factors and RDMs by their rotated forms: f' = U^T f U, B'[X] = U^T B[X] U, every RDM index
  * rotated by the active block of U.  U (n x n, row-major, block-diagonal orthogonal; column
- * j = new orbital j) is written to the caller; f_out (n x n, may be NULL) receives f'.
+ * j = new orbital j, eigenvalues ascending within each block, each column's entry of largest
+ * magnitude positive) is written to the caller; f_out (n x n, may be NULL) receives f'.
  * Amplitudes of the old orbitals transform with the hole and particle blocks of U. */
 int ric_semicanonicalize(ric_ctx* ctx, double* U, double* f_out);
 
@@ -192,6 +233,12 @@ int ric_vec_dot(ric_ctx* ctx, const double* a, const double* b, long n, double* 
 
 /* y <- alpha x + beta y (beta = 0 overwrites y without reading it). */
 int ric_vec_axpby(ric_ctx* ctx, double alpha, const double* x, double beta, double* y, long n);
+
+/* Coefficients of a DIIS extrapolation (host arrays, no device work): with the m x m Gram matrix
+ * G[i][j] = <e_i, e_j> of the error vectors (row-major, m <= 32), c (length m) minimizes
+ * |sum c_i e_i| subject to sum c_i = 1.  If that system is singular to working precision, c selects
+ * the newest vector (c[m-1] = 1).  RIC_E_ARG for m < 1 or m > 32. */
+int ric_diis_coefficients(const double* G, int m, double* c);
 
 /* Milliseconds spent in the ladder during the last ric_residual/ric_ladder call,
  * measured with HIP events on the context stream (host output). */

@@ -50,6 +50,9 @@ hipError_t dot_accumulate(const double* a, const double* b, long n, double alpha
 hipError_t ric_update_kernel(double* t1, double* t2, const double* r1, const double* r2, const double* eps, int nc,
                              int na, int nv, double s, double* partial, double* norm2, hipStream_t st);
 hipError_t fock_diagonal(const double* f, int n, double* eps, hipStream_t st);
+// sign convention of eigenvectors: every column of the m x m block u (row stride ld) gets its entry of
+// largest magnitude (first on ties) positive
+hipError_t column_signs(double* u, int m, long ld, hipStream_t st);
 hipError_t check_finite(const double* x, long n, int* flag, hipStream_t st);
 hipError_t prepare_cumulants(const double* g1, const double* g2, const double* g3, int na, double* ga, double* ea,
                              double* l2, double* k2, double* l3, double* k3, hipStream_t st);

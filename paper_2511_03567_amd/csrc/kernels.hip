@@ -370,6 +370,42 @@ __global__ void column_dot_kernel(const double* __restrict__ B, const double* __
   }
 }
 
+// Column j of the m x m block at u (row stride ld): flip its sign unless its entry of largest
+// magnitude (the first one on ties) is positive.  One workgroup per column.
+__global__ void __launch_bounds__(kThreads) column_sign_kernel(double* __restrict__ u, int m, long ld) {
+  __shared__ double bv[kThreads];
+  __shared__ int bi[kThreads];
+  const int j = blockIdx.x;
+  double best = -1.0;
+  int arg = m;
+  for (int i = threadIdx.x; i < m; i += blockDim.x) {
+    const double a = fabs(u[(long)i * ld + j]);
+    if (a > best) {
+      best = a;
+      arg = i;
+    }
+  }
+  bv[threadIdx.x] = best;
+  bi[threadIdx.x] = arg;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      const double o = bv[threadIdx.x + w];
+      const int oi = bi[threadIdx.x + w];
+      if (o > bv[threadIdx.x] || (o == bv[threadIdx.x] && oi < bi[threadIdx.x])) {
+        bv[threadIdx.x] = o;
+        bi[threadIdx.x] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  const int piv = bi[0];
+  const bool flip = piv < m && u[(long)piv * ld + j] < 0.0;
+  __syncthreads();
+  if (flip)
+    for (int i = threadIdx.x; i < m; i += blockDim.x) u[(long)i * ld + j] = -u[(long)i * ld + j];
+}
+
 __global__ void diag_kernel(const double* __restrict__ f, int n, double* __restrict__ eps) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) eps[i] = f[(long)i * n + i];
 }
@@ -749,6 +785,12 @@ hipError_t ric_update_kernel(double* t1, double* t2, const double* r1, const dou
   hipLaunchKernelGGL(update_kernel, dim3(kRedBlocks), dim3(kThreads), 0, st, t1, t2, r1, r2, eps, nc, na, nv, s,
                      partial);
   hipLaunchKernelGGL(finish_sum, dim3(1), dim3(kThreads), 0, st, partial, kRedBlocks, 1.0, norm2, 0);
+  return hipGetLastError();
+}
+
+hipError_t column_signs(double* u, int m, long ld, hipStream_t st) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(column_sign_kernel, dim3(m), dim3(kThreads), 0, st, u, m, ld);
   return hipGetLastError();
 }
 

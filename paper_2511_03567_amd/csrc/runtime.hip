@@ -250,7 +250,8 @@ struct ric_ctx {
   std::vector<std::string> plan_lines;
   std::vector<Slot> slots;
   std::unordered_map<std::string, int> slot_of;
-  std::map<std::string, std::vector<Op>> sections;  // residual, energy, adjoint_t, adjoint_theta, energy_grad
+  std::map<std::string, std::vector<Op>> sections;  // residual(_lin, _quad), energy, adjoint_t, adjoint_theta, energy_grad
+  std::map<const std::vector<Op>*, std::pair<size_t, size_t>> ladder_block;   // ALLOC TAU .. FREE TAU
 
   // owned device tensors
   DevBuf f, eps, B, BT, BT32, g1, g2, g3, ga, ea, l2, k2, l3, k3, I4, I3, IJ, IK, tau, Edev, red, e0;
@@ -264,6 +265,8 @@ struct ric_ctx {
   bool ladder_ran = false;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   double* noalloc = nullptr;  // this device's copy of `scratch` (set by ric_create)
+  const double* Bp = nullptr;  // the loaded DF factors: the owned copy B, or the caller's array (borrowed)
+  bool accumulate_theta = false;  // adjoint (f, B) parts added to dF, dB instead of overwriting them
 
   ~ric_ctx() {
     for (DevBuf* b : {&f, &eps, &B, &BT, &BT32, &g1, &g2, &g3, &ga, &ea, &l2, &k2, &l3, &k3, &I4, &I3, &IJ, &IK,
@@ -421,8 +424,20 @@ struct ric_ctx {
       if (op.kind == K_CONTRACT || op.kind == K_CONTRACT0 || op.kind == K_DFC) op.text = line;
       cur->push_back(op);
     }
-    for (const char* need : {"residual", "energy", "adjoint_t", "adjoint_theta", "energy_grad"})
+    for (const char* need : {"residual", "residual_lin", "residual_quad", "energy", "adjoint_t", "adjoint_theta",
+                             "energy_grad"})
       if (sections.find(need) == sections.end()) throw Err(RIC_E_PLAN, std::string("plan has no section ") + need);
+    for (auto& kv : sections) {
+      size_t b = kv.second.size(), e = kv.second.size();
+      for (size_t i = 0; i < kv.second.size(); ++i) {
+        const Op& op = kv.second[i];
+        if (op.slot >= 0 && slots[op.slot].name == "TAU") {
+          if (op.kind == K_ALLOC && b == kv.second.size()) b = i;
+          if (op.kind == K_FREE) e = i;
+        }
+      }
+      if (b < kv.second.size() && e < kv.second.size()) ladder_block[&kv.second] = {b, e};
+    }
   }
 
   // -- views ------------------------------------------------------------------------------
@@ -984,7 +999,7 @@ struct ric_ctx {
         it.so[i] = so[i];
         it.si[i] = si[i];
       }
-      HIPCHK(ric::strided_copy(it, 1.0, B.p + nc * n + nc, 0.0, lgb.p, stream));
+      HIPCHK(ric::strided_copy(it, 1.0, Bp + nc * n + nc, 0.0, lgb.p, stream));
     }
     long chunk = std::max<long>(1, (long)(1.4e9 / ((double)np_ * ppad)));
     chunk = std::min(chunk, np_);
@@ -1100,7 +1115,31 @@ struct ric_ctx {
     }
   }
 
-  void run(std::vector<Op>& ops) {
+  // Operations of a section kept under a term mask (ric_residual).  The ladder block, ALLOC TAU
+  // to FREE TAU, runs as a whole or not at all.  Outside it, the operations that act on the
+  // outputs alone (zeroing, symmetrizing and masking R1 and R2) always run; everything else is
+  // a non-ladder term.
+  bool keep_op(const std::vector<Op>& ops, size_t i, unsigned mask) const {
+    if ((mask & (RIC_TERMS_LADDER | RIC_TERMS_NONLADDER)) == (RIC_TERMS_LADDER | RIC_TERMS_NONLADDER)) return true;
+    auto it = ladder_block.find(&ops);
+    if (it != ladder_block.end() && i >= it->second.first && i <= it->second.second)
+      return (mask & RIC_TERMS_LADDER) != 0;
+    const Op& op = ops[i];
+    auto output = [&](int slot) { return slot >= 0 && (slots[slot].name == "R1" || slots[slot].name == "R2"); };
+    if ((op.kind == K_ZERO || op.kind == K_SYMM || op.kind == K_SYMHALF) && output(op.slot)) return true;
+    if (op.kind == K_MASK && output(op.slot) && output(op.slot2)) return true;
+    return (mask & RIC_TERMS_NONLADDER) != 0;
+  }
+
+  // Device memory of a slot that an operation addresses directly; an operation on a tensor
+  // that holds no memory (freed, or never allocated) is a plan error, not a launch.
+  double* live(int slot) {
+    double* p = slots.at(slot).ptr;
+    if (!p && slot_elems(slot) > 0) throw Err(RIC_E_STATE, "tensor " + slots[slot].name + " is not available");
+    return p;
+  }
+
+  void run(std::vector<Op>& ops, unsigned mask = RIC_TERMS_ALL) {
     if (!warmed.count(&ops)) {  // first run of this section: its intermediates enter the pool
       warm_pool(ops);
       warmed.insert(&ops);
@@ -1138,8 +1177,9 @@ struct ric_ctx {
         }
         case K_ZERO: {
           Slot& s = slots[op.slot];
+          if (accumulate_theta && (s.name == "dF" || s.name == "dB")) break;
           if (op.chunked) HIPCHK(ric::fill(loop.buf, loop.len * loop.rest, 0.0, stream));
-          else HIPCHK(ric::fill(s.ptr, slot_elems(op.slot), 0.0, stream));
+          else HIPCHK(ric::fill(live(op.slot), slot_elems(op.slot), 0.0, stream));
           break;
         }
         case K_CONTRACT:
@@ -1165,23 +1205,23 @@ struct ric_ctx {
         case K_ENDLOOP:
           break;
         case K_SYMM:
-          HIPCHK(ric::symmetrize_pairs(slots[op.slot].ptr, sz.nc + sz.na, sz.na + sz.nv, stream));
+          HIPCHK(ric::symmetrize_pairs(live(op.slot), sz.nc + sz.na, sz.na + sz.nv, stream));
           break;
         case K_SYMHALF:
-          HIPCHK(ric::symmetrize_pairs_scaled(slots[op.slot].ptr, sz.nc + sz.na, sz.na + sz.nv, 0.5, stream));
+          HIPCHK(ric::symmetrize_pairs_scaled(live(op.slot), sz.nc + sz.na, sz.na + sz.nv, 0.5, stream));
           break;
         case K_LADDER: {
           HIPCHK(hipEventRecord(ev[0], stream));
-          ladder(slots[op.slot2].ptr, slots[op.slot].ptr);
+          ladder(live(op.slot2), live(op.slot));
           HIPCHK(hipEventRecord(ev[1], stream));
           ladder_ran = true;
           break;
         }
         case K_LADDERGRAD:
-          laddergrad(slots[op.slot].ptr, slots[op.slot2].ptr, slots[op.slot3].ptr);
+          laddergrad(live(op.slot), live(op.slot2), live(op.slot3));
           break;
         case K_MASK:
-          HIPCHK(ric::mask_active(slots[op.slot].ptr, slots[op.slot2].ptr, sz.nc, sz.na, sz.nv, stream));
+          HIPCHK(ric::mask_active(live(op.slot), live(op.slot2), sz.nc, sz.na, sz.nv, stream));
           break;
       }
       if (progress && (op.kind == K_LADDER || op.kind == K_LADDERGRAD || op.kind == K_DFC ||
@@ -1219,11 +1259,15 @@ struct ric_ctx {
     for (size_t oi = 0; oi < ops.size(); ++oi) {
       Op& op = ops[oi];
       if (op.kind != K_LOOP) {
-        step(op);
+        if (keep_op(ops, oi, mask)) step(op);
         continue;
       }
       // the body runs once per chunk of the leading dimension of the chunked intermediate
       const size_t end = (size_t)op.slot3;
+      if (!keep_op(ops, oi, mask)) {
+        oi = end;
+        continue;
+      }
       const auto& decl = slots[op.slot].decl;
       long n = sz.ext(decl.at(0)), rest = 1;
       for (size_t d = 1; d < decl.size(); ++d) rest *= sz.ext(decl[d]);
@@ -1343,6 +1387,7 @@ int ric_set_spaces(ric_ctx* ctx, int nc, int na, int nv, int naux) {
     if (nc < 0 || na < 0 || nv < 0 || naux < 1 || na > 16 || nc + na < 1 || na + nv < 1)
       throw Err(RIC_E_ARG, "invalid orbital space sizes");
     ctx->sz = Sizes{nc, na, nv, naux};
+    ctx->Bp = nullptr;
     ctx->spaces = true;
     ctx->have_f = ctx->have_B = ctx->have_rdm = false;
   });
@@ -1362,20 +1407,26 @@ int ric_load_fock(ric_ctx* ctx, const double* f) {
   });
 }
 
-int ric_load_df(ric_ctx* ctx, const double* B) {
+int ric_load_df(ric_ctx* ctx, const double* B, int borrow) {
   return guard(ctx, [&] {
     if (!ctx->spaces) throw Err(RIC_E_STATE, "ric_set_spaces has not been called");
     if (!B) throw Err(RIC_E_ARG, "null DF factors");
     const Sizes& s = ctx->sz;
     const long n = s.ext(RG), nx = s.naux, nc = s.nc, np_ = s.ext(RP);
-    ctx->B.ensure((size_t)nx * n * n);
-    HIPCHK(hipMemcpyAsync(ctx->B.p, B, (size_t)nx * n * n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
-    ctx->bind("B", ctx->B.p);
+    if (borrow) {
+      ctx->B.release();   // the caller's array is used in place and must outlive its use here
+      ctx->Bp = B;
+    } else {
+      ctx->B.ensure((size_t)nx * n * n);
+      HIPCHK(hipMemcpyAsync(ctx->B.p, B, (size_t)nx * n * n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+      ctx->Bp = ctx->B.p;
+    }
+    ctx->bind("B", ctx->Bp);
     // ladder operand BT[c][e][X] = B[X][nc + c][nc + e]
     ctx->BT.ensure((size_t)np_ * np_ * nx);
     {
       View v;
-      v.p = ctx->B.p + nc * n + nc;
+      v.p = const_cast<double*>(ctx->Bp) + nc * n + nc;
       v.nd = 3;
       v.ext[0] = nx; v.str[0] = n * n; v.lab[0] = 0;
       v.ext[1] = np_; v.str[1] = n; v.lab[1] = 1;
@@ -1446,11 +1497,17 @@ int ric_load_rdms(ric_ctx* ctx, const double* G1, const double* G2, const double
   });
 }
 
-int ric_residual(ric_ctx* ctx, const double* T1, const double* T2, double* R1, double* R2, int precision) {
+int ric_residual(ric_ctx* ctx, const double* T1, const double* T2, double* R1, double* R2, int precision,
+                 unsigned term_mask) {
   return guard(ctx, [&] {
     ctx->require_loaded();
     if (!T1 || !T2 || !R1 || !R2) throw Err(RIC_E_ARG, "null amplitude/residual pointer");
     if (precision != RIC_FP64 && precision != RIC_FP32MIX) throw Err(RIC_E_ARG, "bad precision");
+    if (term_mask & ~(unsigned)RIC_TERMS_ALL) throw Err(RIC_E_ARG, "unknown term group bits");
+    const bool lin = term_mask & RIC_TERMS_LINEAR, quad = term_mask & RIC_TERMS_QUADRATIC;
+    if (!(lin || quad) || !(term_mask & (RIC_TERMS_LADDER | RIC_TERMS_NONLADDER)))
+      throw Err(RIC_E_ARG, "term mask selects no terms");
+    const char* sec = lin && quad ? "residual" : lin ? "residual_lin" : "residual_quad";
     ctx->precision = precision;
     ctx->bind("T1", T1);
     ctx->bind("T2", T2);
@@ -1458,7 +1515,7 @@ int ric_residual(ric_ctx* ctx, const double* T1, const double* T2, double* R1, d
     ctx->bind("R2", R2);
     ctx->ladder_ran = false;
     HIPCHK(hipEventRecord(ctx->ev[2], ctx->stream));
-    ctx->run(ctx->sections.at("residual"));
+    ctx->run(ctx->sections.at(sec), term_mask);
     HIPCHK(hipEventRecord(ctx->ev[3], ctx->stream));
     HIPCHK(hipEventSynchronize(ctx->ev[3]));
     float ms = 0.f;
@@ -1555,7 +1612,7 @@ int ric_ladder(ric_ctx* ctx, const double* tau, double* R2, int precision) {
 }
 
 int ric_adjoint_residual(ric_ctx* ctx, const double* T1, const double* T2, const double* X1, const double* X2,
-                         double* dT1, double* dT2, double* dF, double* dB) {
+                         double* dT1, double* dT2, double* dF, double* dB, int accumulate) {
   return guard(ctx, [&] {
     ctx->require_loaded();
     if (!T1 || !T2 || !X1 || !X2 || !dT1 || !dT2) throw Err(RIC_E_ARG, "null amplitude/cotangent pointer");
@@ -1581,7 +1638,14 @@ int ric_adjoint_residual(ric_ctx* ctx, const double* T1, const double* T2, const
       ctx->bind("dF", dF);
       ctx->bind("dB", dB);
       ctx->release_scratch();  // the (f, B) part holds its own, larger intermediates
-      ctx->run(ctx->sections.at("adjoint_theta"));
+      ctx->accumulate_theta = accumulate != 0;
+      try {
+        ctx->run(ctx->sections.at("adjoint_theta"));
+      } catch (...) {
+        ctx->accumulate_theta = false;
+        throw;
+      }
+      ctx->accumulate_theta = false;
     }
     HIPCHK(hipStreamSynchronize(ctx->stream));
   });
@@ -1666,8 +1730,8 @@ int ric_build_fock(ric_ctx* ctx, const double* h, double* f) {
     gd.C = ctx->scrB.p;
     gd.ldc = 1;
     ctx->scrK.ensure(kSplitScratch);
-    HIPCHK(ric::gemm_nt_f64(gd, ctx->B.p, ctx->scrA.p, st, ctx->scrK.p, ctx->scrK.n));
-    HIPCHK(ric::column_dot(ctx->B.p, ctx->scrB.p, nx, n2, 1.0, f, st));
+    HIPCHK(ric::gemm_nt_f64(gd, ctx->Bp, ctx->scrA.p, st, ctx->scrK.p, ctx->scrK.n));
+    HIPCHK(ric::column_dot(ctx->Bp, ctx->scrB.p, nx, n2, 1.0, f, st));
     // exchange with the core and active orbitals: Y[p][(X,k)] = B[X,p,k] over k in C + A, with
     // the active columns contracted with Gamma1 / 2, then f -= Y Z^T (Z the same gather unweighted)
     const int m = nc + na;
@@ -1683,7 +1747,7 @@ int ric_build_fock(ric_ctx* ctx, const double* h, double* f) {
         it.so[i] = so[i];
         it.si[i] = si[i];
       }
-      HIPCHK(ric::strided_copy(it, 1.0, ctx->B.p, 0.0, ctx->scrC.p, st));
+      HIPCHK(ric::strided_copy(it, 1.0, ctx->Bp, 0.0, ctx->scrC.p, st));
       // weighted copy: core columns as is, active columns Gamma1/2-contracted
       HIPCHK(hipMemcpyAsync(ctx->scrC2.p, ctx->scrC.p, (size_t)n * nx * m * sizeof(double), hipMemcpyDeviceToDevice,
                             st));
@@ -1788,8 +1852,10 @@ int ric_semicanonicalize(ric_ctx* ctx, double* U, double* f_out) {
       HIPCHK(hipMemcpyAsync(&hinfo, info, sizeof(rocblas_int), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
       if (hinfo != 0) throw Err(RIC_E_HIP, "eigensolver did not converge");
-      // column-major eigenvectors: U[o + i][o + j] = blk[j * m + i]
+      // column-major eigenvectors: U[o + i][o + j] = blk[j * m + i], each with its entry of
+      // largest magnitude positive
       copy2d(m, m, blk, 1, m, U + (long)o * n + o, n, 1, st);
+      HIPCHK(ric::column_signs(U + (long)o * n + o, m, n, st));
     }
     (void)hipFree(info);
     ctx->scrB.ensure((size_t)n2 * 3);
@@ -1822,7 +1888,7 @@ int ric_semicanonicalize(ric_ctx* ctx, double* U, double* f_out) {
     gb.ldb = n;
     gb.ldc = n;
     gb.C = ctx->wbuf.p;
-    HIPCHK(ric::gemm_nt_f64(gb, ctx->B.p, Ut, st, scr, nscr));
+    HIPCHK(ric::gemm_nt_f64(gb, ctx->Bp, Ut, st, scr, nscr));
     {  // B1t[X][q'][p] = B1[X][p][q']
       Iter it;
       it.nd = 3;
@@ -1868,7 +1934,7 @@ int ric_semicanonicalize(ric_ctx* ctx, double* U, double* f_out) {
   });
   if (rc != RIC_OK) return rc;
   // outside the guard: the public loaders take the rotated copies
-  rc = ric_load_df(ctx, ctx->sc_B);
+  rc = ric_load_df(ctx, ctx->sc_B, 0);   // copied: the rotated factors sit in a work buffer
   if (rc == RIC_OK && ctx->sz.na > 0) rc = ric_load_rdms(ctx, ctx->sc_g[0], ctx->sc_g[1], ctx->sc_g[2]);
   ctx->sc_B = nullptr;
   return guard(ctx, [&] {
@@ -1902,6 +1968,88 @@ int ric_vec_axpby(ric_ctx* ctx, double alpha, const double* x, double beta, doub
     it.total = n;
     HIPCHK(ric::strided_copy(it, alpha, x, beta, y, ctx->stream));
   });
+}
+
+int ric_layout(const ric_ctx* ctx, ric_layout_t* out) {
+  if (!ctx || !out) return RIC_E_ARG;
+  if (!ctx->spaces) return RIC_E_STATE;
+  const Sizes& z = ctx->sz;
+  const int nc = z.nc, na = z.na, nv = z.nv, nh = nc + na, np = na + nv;
+  std::memset(out, 0, sizeof(*out));
+  out->nc = nc;
+  out->na = na;
+  out->nv = nv;
+  out->naux = z.naux;
+  out->nh = nh;
+  out->np = np;
+  out->t1_elems = (long)nh * np;
+  out->t2_elems = (long)nh * nh * np * np;
+  // hole ranges: core [0, nc), active [nc, nh); particle ranges: active [0, na), virtual [na, np)
+  struct R { int s, e; };
+  const R Ch{0, nc}, Ah{nc, na}, Ap{0, na}, Vp{na, nv};
+  struct Cls { const char* name; int rank; R r[4]; };
+  const Cls cls[12] = {
+      {"IA", 1, {Ch, Vp}},           {"IT", 1, {Ch, Ap}},           {"TA", 1, {Ah, Vp}},
+      {"IJAB", 2, {Ch, Ch, Vp, Vp}}, {"IJTU", 2, {Ch, Ch, Ap, Ap}}, {"TUAB", 2, {Ah, Ah, Vp, Vp}},
+      {"ITAB", 2, {Ch, Ah, Vp, Vp}}, {"ITUV", 2, {Ch, Ah, Ap, Ap}}, {"IJTA", 2, {Ch, Ch, Ap, Vp}},
+      {"TUVA", 2, {Ah, Ah, Ap, Vp}}, {"ITUA1", 2, {Ch, Ah, Ap, Vp}}, {"ITUA2", 2, {Ch, Ah, Vp, Ap}}};
+  out->nblocks = 12;
+  for (int b = 0; b < 12; ++b) {
+    ric_block_t& o = out->block[b];
+    std::snprintf(o.name, sizeof(o.name), "%s", cls[b].name);
+    o.rank = cls[b].rank;
+    for (int i = 0; i < 2 * cls[b].rank; ++i) {
+      o.start[i] = cls[b].r[i].s;
+      o.extent[i] = cls[b].r[i].e;
+    }
+  }
+  return RIC_OK;
+}
+
+int ric_diis_coefficients(const double* G, int m, double* c) {
+  if (!G || !c || m < 1 || m > 32) return RIC_E_ARG;
+  // bordered system [G 1; 1^T 0] [c; mu] = [0; 1], G scaled by its largest diagonal element;
+  // Gaussian elimination with partial pivoting
+  const int n = m + 1;
+  double a[33][34];
+  double scale = 0.0;
+  for (int i = 0; i < m; ++i) scale = std::max(scale, std::fabs(G[i * m + i]));
+  if (!(scale > 0.0) || !std::isfinite(scale)) scale = 1.0;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j <= n; ++j) a[i][j] = 0.0;
+  for (int i = 0; i < m; ++i) {
+    for (int j = 0; j < m; ++j) a[i][j] = G[i * m + j] / scale;
+    a[i][m] = 1.0;
+    a[m][i] = 1.0;
+  }
+  a[m][n] = 1.0;
+  bool singular = false;
+  for (int k = 0; k < n && !singular; ++k) {
+    int p = k;
+    for (int i = k + 1; i < n; ++i)
+      if (std::fabs(a[i][k]) > std::fabs(a[p][k])) p = i;
+    if (!(std::fabs(a[p][k]) > 1e-14)) {
+      singular = true;
+      break;
+    }
+    if (p != k)
+      for (int j = 0; j <= n; ++j) std::swap(a[p][j], a[k][j]);
+    for (int i = k + 1; i < n; ++i) {
+      const double f = a[i][k] / a[k][k];
+      for (int j = k; j <= n; ++j) a[i][j] -= f * a[k][j];
+    }
+  }
+  double x[33];
+  if (!singular) {
+    for (int i = n - 1; i >= 0; --i) {
+      double v = a[i][n];
+      for (int j = i + 1; j < n; ++j) v -= a[i][j] * x[j];
+      x[i] = v / a[i][i];
+    }
+    for (int i = 0; i < m; ++i) singular = singular || !std::isfinite(x[i]);
+  }
+  for (int i = 0; i < m; ++i) c[i] = singular ? (i == m - 1 ? 1.0 : 0.0) : x[i];
+  return RIC_OK;
 }
 
 int ric_last_timings(const ric_ctx* ctx, double* ladder_ms, double* total_ms) {

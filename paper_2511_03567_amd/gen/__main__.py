@@ -19,15 +19,17 @@ def main():
     t0 = time.time()
     if args.terms_cache and os.path.exists(args.terms_cache):
         with open(args.terms_cache, "rb") as fh:
-            e, r1, s2 = pickle.load(fh)
+            e, groups = pickle.load(fh)
     else:
-        e, r1, s2 = algebra.derive()
+        e, groups = algebra.derive_groups()
         if args.terms_cache:
             with open(args.terms_cache, "wb") as fh:
-                pickle.dump((e, r1, s2), fh)
-    s2 = algebra.merge_pair_images(s2)   # idempotent; also applied to cached term lists
+                pickle.dump((e, groups), fh)
+    # the whole residual: both groups merged, doubles merged modulo the pair swap
+    r1 = algebra.merge_sf(groups["lin"][0] + groups["quad"][0])
+    s2 = algebra.merge_pair_images(algebra.merge_sf(groups["lin"][1] + groups["quad"][1]))
     t1 = time.time()
-    plan, res_flops = comp.compile_plan(e, r1, s2)
+    plan, res_flops = comp.compile_plan(e, r1, s2, groups=groups)
     text = "\n".join(plan.lines) + "\n"
     here = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     with open(os.path.join(here, "plan.txt"), "w") as fh:

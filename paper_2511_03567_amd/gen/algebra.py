@@ -496,7 +496,16 @@ T3_BLOCKS = [(C, A, A, A), (A, C, A, A), (A, A, A, V), (A, A, V, A)]
 
 
 def derive():
-    """Spin-free terms of E_corr, R1[k,c] and S2[k,l,c,d] (R2 = S2 + S2 with both pairs swapped).
+    """Spin-free terms of E_corr, R1[k,c] and S2[k,l,c,d] (R2 = S2 + S2 with both pairs swapped)."""
+    e, groups = derive_groups()
+    r1 = merge_sf(groups["lin"][0] + groups["quad"][0])
+    s2 = merge_pair_images(merge_sf(groups["lin"][1] + groups["quad"][1]))
+    return e, r1, s2
+
+
+def derive_groups():
+    """Spin-free terms of E_corr, and of R1 and S2 by term group: "lin" (H + [H,T]) and "quad"
+    (the filtered two-fold commutator), each group merged on its own.
 
     Linear part: H + [H,T] in full.  Two-fold commutator (Section 2.2):
       residuals: 1/2 ([[H,Te],T] + [[H,T],Te] - [[H,Te],Te]) without two-body cumulants,
@@ -519,9 +528,13 @@ def derive():
         for rb2 in T3_BLOCKS:
             quadE += [(Fraction(-1, 2), q) for q in commutator(Xb, cluster(None, rb2), 0)]
 
-    e_terms, r1_terms, s2_terms = [], [], []
-    items = [(Fraction(1), t) for t in lin] + quadR + quadE
-    for c, t in items:
+    e_terms = []
+    r1_by = {"lin": [], "quad": []}
+    s2_by = {"lin": [], "quad": []}
+    items = ([(Fraction(1), t, "lin") for t in lin] + [(c, q, "quad") for c, q in quadR]
+             + [(c, q, "quad") for c, q in quadE])
+    for c, t, grp in items:
+        r1_terms, s2_terms = r1_by[grp], s2_by[grp]
         t = SOTerm(t.coef * c, t.tensors, t.upper, t.lower, t.rng, t.has_l2)
         r = t.rank()
         if r == 0:
@@ -551,4 +564,5 @@ def derive():
             s2_terms += spin_integrate(t2, (l1, l2, u1, u2), (0, 1, 0, 1))
             neg = SOTerm(-t.coef, t.tensors, t.upper, t.lower, rr, t.has_l2)
             s2_terms += spin_integrate(neg, (l1, l2, u2, u1), (0, 1, 0, 1))
-    return merge_sf(e_terms), merge_sf(r1_terms), merge_pair_images(merge_sf(s2_terms))
+    groups = {g: (merge_sf(r1_by[g]), merge_pair_images(merge_sf(s2_by[g]))) for g in ("lin", "quad")}
+    return merge_sf(e_terms), groups

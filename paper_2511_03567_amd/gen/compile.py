@@ -366,19 +366,20 @@ def _emit_tau(plan, ladder):
     plan.lines.append("SYMMETRIZE TAU")
 
 
-def compile_plan(e_terms, r1_terms, s2_terms, adjoint=True):
-    plan = Plan()
+def _emit_residual(plan, name, r1_terms, s2_terms):
+    """One residual section: the non-ladder terms into R1 and S2, R2 = S2 + S2^T(pairs), then the
+    ladder (tau accumulated and symmetrized over pairs, contracted with (ce|df) built from B).
+    The ladder block runs from ALLOC TAU to FREE TAU.  Returns the section's ladder terms."""
     res = _Terms()
     for t in r1_terms:
         res.add_sf(t, "R1", (t.rng[t.ext[0]], t.rng[t.ext[1]]))
     for t in s2_terms:
         res.add_sf(t, "R2", tuple(t.rng[l] for l in t.ext))
-    plan.lines.append("SECTION residual")
+    plan.lines.append(f"SECTION {name}")
     plan.lines.append("ZERO R1")
     plan.lines.append("ZERO R2")
     res.emit(plan)
     plan.lines.append("SYMMETRIZE R2")
-    # ladder: tau accumulated, symmetrized over pairs, contracted with (ce|df) from B
     if res.ladder:
         _emit_tau(plan, res.ladder)
         plan.lines.append("LADDER R2 TAU")
@@ -388,7 +389,20 @@ def compile_plan(e_terms, r1_terms, s2_terms, adjoint=True):
         plan.lines.append("FREE TAU")
     plan.lines.append("MASK R1 R2")
     plan.lines.append("END")
+    return res.ladder
+
+
+def compile_plan(e_terms, r1_terms, s2_terms, adjoint=True, groups=None):
+    """groups: optional {"lin": (r1, s2), "quad": (r1, s2)}, compiled into the sections
+    residual_lin and residual_quad (the term groups a caller may evaluate on their own)."""
+    plan = Plan()
+    ladder = _emit_residual(plan, "residual", r1_terms, s2_terms)
     res_flops = plan.flops
+    if groups is not None:
+        for g in ("lin", "quad"):
+            f0, l0 = plan.flops, plan.ladder_flops
+            _emit_residual(plan, f"residual_{g}", *groups[g])
+            plan.flops, plan.ladder_flops = f0, l0
     # energy: every term is a full contraction
     plan.lines.append("SECTION energy")
     plan.lines.append("ZERO E")
@@ -398,7 +412,7 @@ def compile_plan(e_terms, r1_terms, s2_terms, adjoint=True):
     en.emit(plan)
     plan.lines.append("END")
     if adjoint:
-        compile_adjoint(plan, e_terms, r1_terms, s2_terms, res.ladder)
+        compile_adjoint(plan, e_terms, r1_terms, s2_terms, ladder)
     return plan, res_flops
 
 

@@ -18,12 +18,30 @@ PLAN_PATH = os.path.join(_HERE, "plan.txt")
 RIC_FP64 = 0
 RIC_FP32MIX = 1
 
+# term groups of ric_residual
+RIC_TERMS_LINEAR = 1
+RIC_TERMS_QUADRATIC = 2
+RIC_TERMS_LADDER = 4
+RIC_TERMS_NONLADDER = 8
+RIC_TERMS_ALL = 15
+
 RIC_E_NOCONV = -7   # raised by solve() only: the iteration did not reach the tolerance
 
 _ERRORS = {-1: "RIC_E_ARG", -2: "RIC_E_STATE", -3: "RIC_E_OOM", -4: "RIC_E_HIP",
            -5: "RIC_E_NONFINITE", -6: "RIC_E_PLAN", RIC_E_NOCONV: "RIC_E_NOCONV"}
 
 _lib = None
+
+
+class Block(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 8), ("rank", ctypes.c_int), ("start", ctypes.c_int * 4),
+                ("extent", ctypes.c_int * 4)]
+
+
+class Layout(ctypes.Structure):
+    _fields_ = [("nc", ctypes.c_int), ("na", ctypes.c_int), ("nv", ctypes.c_int), ("naux", ctypes.c_int),
+                ("nh", ctypes.c_int), ("np", ctypes.c_int), ("t1_elems", ctypes.c_long), ("t2_elems", ctypes.c_long),
+                ("nblocks", ctypes.c_int), ("block", Block * 12)]
 
 
 class RicError(RuntimeError):
@@ -48,15 +66,17 @@ def library():
     lib.ric_destroy.restype = None
     lib.ric_set_spaces.argtypes = [P, I, I, I, I]
     lib.ric_load_fock.argtypes = [P, P]
-    lib.ric_load_df.argtypes = [P, P]
+    lib.ric_load_df.argtypes = [P, P, I]
+    lib.ric_layout.argtypes = [P, ctypes.POINTER(Layout)]
+    lib.ric_diis_coefficients.argtypes = [ctypes.POINTER(D), I, ctypes.POINTER(D)]
     lib.ric_load_rdms.argtypes = [P, P, P, P]
-    lib.ric_residual.argtypes = [P, P, P, P, P, I]
+    lib.ric_residual.argtypes = [P, P, P, P, P, I, ctypes.c_uint]
     lib.ric_update.argtypes = [P, P, P, P, P, D, ctypes.POINTER(D)]
     lib.ric_update_noalloc.argtypes = [P, P, P, P, P, D, ctypes.POINTER(D)]
     lib.ric_energy.argtypes = [P, P, P, ctypes.POINTER(D), ctypes.POINTER(D)]
     lib.ric_ladder.argtypes = [P, P, P, I]
     lib.ric_last_timings.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(D)]
-    lib.ric_adjoint_residual.argtypes = [P] * 9
+    lib.ric_adjoint_residual.argtypes = [P] * 9 + [I]
     lib.ric_energy_gradient.argtypes = [P] * 7
     lib.ric_lambda_update.argtypes = [P] * 7 + [D, ctypes.POINTER(D)]
     lib.ric_flow_scale.argtypes = [P, P, P, D, P, P]
@@ -71,7 +91,7 @@ def library():
                "ric_residual", "ric_update", "ric_update_noalloc", "ric_energy", "ric_ladder", "ric_last_timings",
                "ric_adjoint_residual", "ric_energy_gradient", "ric_lambda_update", "ric_flow_scale",
                "ric_flow_fock_gradient", "ric_vec_dot", "ric_vec_axpby", "ric_build_fock",
-               "ric_semicanonicalize"):
+               "ric_semicanonicalize", "ric_layout", "ric_diis_coefficients"):
         getattr(lib, fn).restype = I
     _lib = lib
     return lib
@@ -135,8 +155,21 @@ class Context:
     def load_fock(self, f):
         self._check(self.lib.ric_load_fock(self.h, _ptr(f, (self.n, self.n), "f")))
 
-    def load_df(self, B):
-        self._check(self.lib.ric_load_df(self.h, _ptr(B, (self.sizes[3], self.n, self.n), "B")))
+    def load_df(self, B, borrow=False):
+        """DF factors; borrow=True uses the tensor in place (it is kept referenced here until the
+        next load_df) instead of copying it."""
+        self._check(self.lib.ric_load_df(self.h, _ptr(B, (self.sizes[3], self.n, self.n), "B"), int(bool(borrow))))
+        self._B_borrowed = B if borrow else None
+
+    def layout(self):
+        """The amplitude classes of the dense T1/T2 layout: {name: (rank, starts, extents)}."""
+        out = Layout()
+        self._check(self.lib.ric_layout(self.h, ctypes.byref(out)))
+        blocks = {}
+        for b in out.block[:out.nblocks]:
+            r = 2 * b.rank
+            blocks[b.name.decode()] = (b.rank, tuple(b.start[:r]), tuple(b.extent[:r]))
+        return blocks
 
     def load_rdms(self, G1, G2, G3):
         na = self.sizes[1]
@@ -147,10 +180,10 @@ class Context:
     def amplitude_shapes(self):
         return (self.nH, self.nP), (self.nH, self.nH, self.nP, self.nP)
 
-    def residual(self, T1, T2, R1, R2, precision=RIC_FP64):
+    def residual(self, T1, T2, R1, R2, precision=RIC_FP64, terms=RIC_TERMS_ALL):
         s1, s2 = self.amplitude_shapes()
         self._check(self.lib.ric_residual(self.h, _ptr(T1, s1, "T1"), _ptr(T2, s2, "T2"),
-                                          _ptr(R1, s1, "R1"), _ptr(R2, s2, "R2"), int(precision)))
+                                          _ptr(R1, s1, "R1"), _ptr(R2, s2, "R2"), int(precision), int(terms)))
 
     def update(self, T1, T2, R1, R2, s):
         s1, s2 = self.amplitude_shapes()
@@ -180,13 +213,15 @@ class Context:
         self._check(self.lib.ric_ladder(self.h, _ptr(tau, s2, "tau"), _ptr(R2, s2, "R2"), int(precision)))
 
     # --- adjoint -----------------------------------------------------------------------
-    def adjoint_residual(self, T1, T2, X1, X2, dT1, dT2, dF=None, dB=None):
-        """dT = (dr/dT)^T x; with dF, dB also (dr/df)^T x and (dr/dB)^T x."""
+    def adjoint_residual(self, T1, T2, X1, X2, dT1, dT2, dF=None, dB=None, accumulate=False):
+        """dT = (dr/dT)^T x; with dF, dB also (dr/df)^T x and (dr/dB)^T x (added to dF, dB when
+        accumulate is true)."""
         s1, s2 = self.amplitude_shapes()
         n, nx = self.n, self.sizes[3]
         self._check(self.lib.ric_adjoint_residual(
             self.h, _ptr(T1, s1, "T1"), _ptr(T2, s2, "T2"), _ptr(X1, s1, "X1"), _ptr(X2, s2, "X2"),
-            _ptr(dT1, s1, "dT1"), _ptr(dT2, s2, "dT2"), _ptr(dF, (n, n), "dF"), _ptr(dB, (nx, n, n), "dB")))
+            _ptr(dT1, s1, "dT1"), _ptr(dT2, s2, "dT2"), _ptr(dF, (n, n), "dF"), _ptr(dB, (nx, n, n), "dB"),
+            int(bool(accumulate))))
 
     def energy_gradient(self, T1, T2, dT1, dT2, dF, dB):
         s1, s2 = self.amplitude_shapes()
@@ -257,6 +292,18 @@ def masks(nc, na, nv, device):
     return m1, m2
 
 
+def diis_coefficients(G):
+    """ric_diis_coefficients: weights c with sum c_i = 1 minimizing |sum c_i e_i|, from the
+    Gram matrix G[i][j] = <e_i, e_j> (host code of the library; needs no device)."""
+    m = int(G.shape[0])
+    Gc = (ctypes.c_double * (m * m))(*[float(x) for x in np.asarray(G, dtype=np.float64).reshape(-1)])
+    cc = (ctypes.c_double * m)()
+    rc = library().ric_diis_coefficients(Gc, m, cc)
+    if rc != 0:
+        raise RicError(rc, f"ric_diis_coefficients: m = {m}")
+    return list(cc)
+
+
 class _Diis:
     """Pulay's direct inversion in the iterative subspace over amplitude pairs (T1, T2).
 
@@ -293,13 +340,7 @@ class _Diis:
         m = len(self.U)
         if m < 2:
             return False
-        A = np.zeros((m + 1, m + 1))
-        scale = max(np.abs(np.diag(self.B)).max(), 1e-300)
-        A[:m, :m] = self.B / scale
-        A[m, :m] = A[:m, m] = -1.0
-        rhs = np.zeros(m + 1)
-        rhs[m] = -1.0
-        c = np.linalg.lstsq(A, rhs, rcond=None)[0][:m]
+        c = diis_coefficients(self.B)
         for T, k in ((T1, 0), (T2, 1)):
             for j in range(m):
                 self.ctx.axpby(c[j], self.U[j][k], 0.0 if j == 0 else 1.0, T)
@@ -395,13 +436,10 @@ def energy_gradient(ctx: Context, T1, T2, s, tol=1e-10, max_iter=400, diis=0):
     P2 = torch.zeros(s2, dtype=torch.float64, device=dev)
     ctx.flow_scale(L1, L2, s, P1, P2)
     J1, J2 = torch.empty_like(P1), torch.empty_like(P2)
-    rF, rB = torch.empty_like(dF), torch.empty_like(dB)
-    ctx.adjoint_residual(T1, T2, P1, P2, J1, J2, rF, rB)
+    ctx.adjoint_residual(T1, T2, P1, P2, J1, J2, dF, dB, accumulate=True)   # dE/d(f,B) at fixed T + (dr/d(f,B))^T(phi L)
     R1, R2 = torch.empty_like(P1), torch.empty_like(P2)
     ctx.residual(T1, T2, R1, R2)
-    dF.add_(rF)
-    dB.add_(rB)
-    ctx.flow_fock_gradient(T1, T2, R1, R2, L1, L2, s, dF)
+    ctx.flow_fock_gradient(T1, T2, R1, R2, L1, L2, s, dF)                    # + the denominators' part
     return dF, dB
 
 
@@ -430,5 +468,7 @@ class RICEnergy(torch.autograd.Function):
         ctx.load_fock(f)     # the context may have been used for other inputs since forward
         ctx.load_df(B)
         dF, dB = energy_gradient(ctx, T1, T2, s, tol)
-        g = grad.to(dF.dtype)
-        return g * dF, g * dB, None, None, None
+        g = float(grad)
+        ctx.axpby(0.0, dF, g, dF)     # chain rule: scale by the incoming gradient, on the device
+        ctx.axpby(0.0, dB, g, dB)
+        return dF, dB, None, None, None

@@ -202,7 +202,65 @@ def spinorbital_rdms(dets, coeffs, na: int, kmax: int = 3):
     return out
 
 
+def _annihilation_table_sorted(dets, coeffs, nso: int, k: int):
+    """Entries of a_qk .. a_q1 |Psi> for increasing q1 < .. < qk only, as (det, amp, tuple code)."""
+    cur = [(dets.astype(np.uint64), coeffs.astype(np.float64), np.zeros(dets.size, dtype=np.int64), -1)]
+    for _ in range(k):
+        nxt = []
+        for d, a, c, last in cur:
+            for q in range(last + 1, nso):
+                d2, a2, c2 = _annihilate(d, a, c, q, nso)
+                if d2.size:
+                    nxt.append((d2, a2, c2 * nso + q, q))
+        cur = nxt
+    if not cur:
+        return (np.zeros(0, dtype=np.uint64), np.zeros(0), np.zeros(0, dtype=np.int64))
+    return (np.concatenate([x[0] for x in cur]), np.concatenate([x[1] for x in cur]),
+            np.concatenate([x[2] for x in cur]))
+
+
 def spinfree_rdms(dets, coeffs, na: int, kmax: int = 3):
+    """Spin-free RDMs Gamma^{P1..Pk}_{Q1..Qk} summed over column spins, k = 1..kmax.
+
+    The spin-orbital RDM is formed over increasing index tuples only (the Gram matrix of
+    a_qk .. a_q1 |Psi> for q1 < .. < qk); an element with its indices in another order is that
+    value times the sign of the sorting permutation, and repeated indices give zero.
+    """
+    nso = 2 * na
+    out = []
+    for k in range(1, kmax + 1):
+        d, a, c = _annihilation_table_sorted(dets, coeffs, nso, k)
+        codes, col = np.unique(c, return_inverse=True) if c.size else (np.zeros(0, dtype=np.int64), c)
+        g = _gram(d, a, col, max(codes.size, 1))
+        # column of every ordered spin-orbital tuple: (spatial tuple, spin pattern) -> (sorted column, sign)
+        where = {int(x): i for i, x in enumerate(codes)}
+        nsp = na ** k
+        G = np.zeros((nsp, nsp))
+        for pat in itertools.product((0, 1), repeat=k):
+            cols = np.full(nsp, -1, dtype=np.int64)
+            sgn = np.zeros(nsp)
+            for j, P in enumerate(itertools.product(range(na), repeat=k)):
+                q = [P[i] + pat[i] * na for i in range(k)]
+                if len(set(q)) < k:
+                    continue
+                order = sorted(range(k), key=lambda i: q[i])
+                inv = sum(1 for x in range(k) for y in range(x + 1, k) if order[y] < order[x])
+                code = 0
+                for i in order:
+                    code = code * nso + q[i]
+                if code in where:
+                    cols[j] = where[code]
+                    sgn[j] = -1.0 if inv % 2 else 1.0
+            ok = cols >= 0
+            if not np.any(ok):
+                continue
+            sub = g[np.ix_(cols[ok], cols[ok])] * np.outer(sgn[ok], sgn[ok])
+            G[np.ix_(ok, ok)] += sub
+        out.append(G.reshape((na,) * (2 * k)))
+    return out
+
+
+def spinfree_rdms_ordered(dets, coeffs, na: int, kmax: int = 3):
     """Spin-free RDMs Gamma^{P1..Pk}_{Q1..Qk} summed over column spins, k = 1..kmax.
 
     Gamma[P1..Pk, Q1..Qk] = sum_{s1..sk} <a^+_{P1 s1} .. a^+_{Pk sk} a_{Qk sk} .. a_{Q1 s1}>.

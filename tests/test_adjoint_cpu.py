@@ -83,7 +83,7 @@ def test_residual_vjp_amplitudes(plan_text, nc, na, nv, naux, seed):
     out = _run(plan_text, "adjoint_t", cfg, inp, T, x)
     want = _dot(x, jv)
     got = _dot((out["dT1"], out["dT2"]), v)
-    assert abs(got - want) <= 1e-9 * max(1.0, abs(want))
+    assert abs(got - want) <= 1e-9 * abs(want)
     d2 = out["dT2"]
     assert np.array_equal(d2, d2.transpose(1, 0, 3, 2))
 
@@ -98,7 +98,7 @@ def test_residual_vjp_fock_and_df(plan_text, nc, na, nv, naux, seed):
     jf = [(a - b) / (2 * H) for a, b in zip(*rf)]
     jb = [(a - b) / (2 * H) for a, b in zip(*rb)]
     for want, got in ((_dot(x, jf), float(np.sum(out["dF"] * df))), (_dot(x, jb), float(np.sum(out["dB"] * dB)))):
-        assert abs(got - want) <= 1e-9 * max(1.0, abs(want))
+        assert abs(got - want) <= 1e-9 * abs(want)
 
 
 @pytest.mark.parametrize("nc,na,nv,naux,seed", CASES)
@@ -114,4 +114,4 @@ def test_energy_gradient(plan_text, nc, na, nv, naux, seed):
           - R.Reference(nc, na, nv, inp.f, inp.B - H * dB, *G).energy(*T)) / (2 * H)
     got = [_dot((out["dT1"], out["dT2"]), v), float(np.sum(out["dF"] * df)), float(np.sum(out["dB"] * dB))]
     for g, w in zip(got, (et, ef, eb)):
-        assert abs(g - w) <= 1e-9 * max(1.0, abs(w))
+        assert abs(g - w) <= 1e-9 * abs(w)

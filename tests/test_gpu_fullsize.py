@@ -6,10 +6,11 @@ The amplitudes vanish outside a few cores and virtuals spread over the index ran
 ragged last tile, interior ones).  Every residual element whose indices lie in those
 cores + all actives + those virtuals, and the correlation energy, then equal the
 oracle's on the problem restricted to those orbitals; test_subset_cpu.py checks that
-reduction with the oracle alone.  Bar: 1e-10 relative on the FP64 residuals, 1e-5 on
+reduction with the oracle alone.  Bar: 1e-10 relative (max |diff| / max |oracle|) on the FP64 residuals, 1e-5 on
 the FP32-mixed residuals (FP32 MFMA tiles with FP64 accumulation per slab), 1e-9 E_h on
 the energy.  The regularized update, elementwise in the diagonal of f, is checked on the
-same elements against the oracle's update of the sampled residual, to 1e-14.
+same elements against the oracle's update of the oracle's own residual, to 1e-13 (the
+residuals' rounding differences pass through the update's factor).
 
 The adjoint (dT = J_r^T x) reduces the same way when x also vanishes outside the subset:
 along amplitude directions inside the subset the full residual and the restricted one are
@@ -104,23 +105,23 @@ def test_fullsize_residual_and_energy_sampled():
 
     sub = R.Reference(ncs, na, nvs, fs, Bs, G1, G2, G3)
     R1o, R2o = sub.residual(T1s, T2s)
-    r1 = float(np.abs(R1g - R1o).max() / max(1.0, np.abs(R1o).max()))
-    r2 = float(np.abs(R2g - R2o).max() / max(1.0, np.abs(R2o).max()))
-    x1 = float(np.abs(R1m - R1o).max() / max(1.0, np.abs(R1o).max()))
-    x2 = float(np.abs(R2m - R2o).max() / max(1.0, np.abs(R2o).max()))
+    r1 = float(np.abs(R1g - R1o).max() / np.abs(R1o).max())
+    r2 = float(np.abs(R2g - R2o).max() / np.abs(R2o).max())
+    x1 = float(np.abs(R1m - R1o).max() / np.abs(R1o).max())
+    x2 = float(np.abs(R2m - R2o).max() / np.abs(R2o).max())
     print(f"  residual rel diff FP64: R1 {r1:.2e} R2 {r2:.2e}; FP32-mixed: R1 {x1:.2e} R2 {x2:.2e}", flush=True)
     eo = sub.energy(T1s, T2s)
     print(f"  energy {e:.12f} oracle {eo:.12f} |dE| {abs(e - eo):.2e}; {time.perf_counter() - t0:.1f} s",
           flush=True)
     D1, D2 = R.denominators(fs, ncs, na, nvs)
-    N1 = R.ric_update(T1s, R1g, D1, cfg.s) * m1
-    N2 = R.ric_update(T2s, R2g, D2, cfg.s) * m2
-    u1 = float(np.abs(U1 - N1).max() / max(1.0, np.abs(N1).max()))
-    u2 = float(np.abs(U2 - N2).max() / max(1.0, np.abs(N2).max()))
+    N1 = R.ric_update(T1s, R1o, D1, cfg.s) * m1
+    N2 = R.ric_update(T2s, R2o, D2, cfg.s) * m2
+    u1 = float(np.abs(U1 - N1).max() / np.abs(N1).max())
+    u2 = float(np.abs(U2 - N2).max() / np.abs(N2).max())
     print(f"  update rel diff T1 {u1:.2e} T2 {u2:.2e}", flush=True)
     assert r1 < 1e-10 and r2 < 1e-10
     assert x1 < 1e-5 and x2 < 1e-5
-    assert u1 < 1e-14 and u2 < 1e-14
+    assert u1 < 1e-13 and u2 < 1e-13
     assert abs(e - eo) < 1e-9
 
 
@@ -198,7 +199,7 @@ def test_fullsize_adjoint_residual_sampled():
     rm = sub.residual(T[0] - H * v[0], T[1] - H * v[1])
     want = float(sum(np.sum(a * (b - c)) for a, b, c in zip(x, rp, rm)) / (2 * H))
     got = float(np.sum(d1 * v[0]) + np.sum(d2 * v[1]))
-    print(f"  <dT, v> {got:.12e}  <x, J v> {want:.12e}  rel {abs(got - want) / max(1.0, abs(want)):.2e}; "
+    print(f"  <dT, v> {got:.12e}  <x, J v> {want:.12e}  rel {abs(got - want) / abs(want):.2e}; "
           f"{time.perf_counter() - t0:.1f} s", flush=True)
-    assert abs(got - want) <= 1e-9 * max(1.0, abs(want))
+    assert abs(got - want) <= 1e-9 * abs(want)
     assert sym and masked

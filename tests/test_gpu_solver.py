@@ -33,9 +33,9 @@ def _ctx(cfg):
     return ctx
 
 
-def _golden():
+def _golden(key="cases"):
     with open(GOLDEN) as fh:
-        return json.load(fh)["cases"]
+        return json.load(fh).get(key, [])
 
 
 @pytest.mark.parametrize("case", _golden(), ids=lambda c: f"{c['config']}-s{c['s']}")
@@ -50,6 +50,29 @@ def test_solve_matches_oracle(case):
     assert abs(e0 - case["e0"]) < 1e-9
     assert abs(e64 - case["e_corr"]) < 1e-9
     assert abs(it64 - case["iterations"]) <= 1
+    assert abs(emx - case["e_corr"]) < 1e-6
+
+
+@pytest.mark.parametrize("case", _golden("diis_cases"), ids=lambda c: f"{c['config']}-s{c['s']}")
+def test_diis_solve_matches_oracle_cas88(case):
+    """CAS(8,8) (nc=10, nv=120, naux=360): converged E_corr against the oracle's own fixed point
+    (DIIS over the oracle's update, make_solve_golden.py --diis): FP64 within 1e-8 E_h,
+    FP32-mixed iterations with FP64 polish within 1e-6 E_h."""
+    from paper_2511_03567_amd import ric
+    cfg = S.CONFIGS[case["config"]]
+    print(f"DIIS solve {case['config']} s={case['s']}", flush=True)
+    ctx = _ctx(cfg)
+    t0 = time.perf_counter()
+    e64, e0, _, _, it64 = ric.solve(ctx, case["s"], tol=case["tol"], diis=case["diis"])
+    t1 = time.perf_counter()
+    emx, _, _, _, itmx = ric.solve(ctx, case["s"], tol=case["tol"], diis=case["diis"],
+                                   precision=ric.RIC_FP32MIX)
+    t2 = time.perf_counter()
+    print(f"  fp64 {e64:.12f} ({it64} it, {t1 - t0:.1f} s)  mixed {emx:.12f} ({itmx} it, {t2 - t1:.1f} s)  "
+          f"oracle {case['e_corr']:.12f}  |dE| fp64 {abs(e64 - case['e_corr']):.2e} "
+          f"mixed {abs(emx - case['e_corr']):.2e}", flush=True)
+    assert abs(e0 - case["e0"]) < 1e-9
+    assert abs(e64 - case["e_corr"]) < 1e-8
     assert abs(emx - case["e_corr"]) < 1e-6
 
 

@@ -78,3 +78,45 @@ def test_diis_extrapolation_solves_a_linear_fixed_point():
     it_diis, x_diis = run(n + 2)
     assert it_diis is not None and np.abs(x_diis - exact).max() < 1e-9
     assert it_plain is None or it_diis < it_plain / 4
+
+
+def test_diis_coefficients_solve_the_constrained_least_squares():
+    """ric_diis_coefficients (host code of the library, no GPU): c minimizes |sum c_i e_i| with
+    sum c_i = 1; checked against numpy's solution of the bordered system on random error vectors,
+    and the fallback to the newest vector when the Gram matrix is singular."""
+    import ctypes
+    lib_path = os.path.join(ROOT, "paper_2511_03567_amd", "libricmrcc.so")
+    if not os.path.exists(lib_path):
+        pytest.skip("library not built")
+    lib = ctypes.CDLL(lib_path)
+    D = ctypes.c_double
+    lib.ric_diis_coefficients.argtypes = [ctypes.POINTER(D), ctypes.c_int, ctypes.POINTER(D)]
+    lib.ric_diis_coefficients.restype = ctypes.c_int
+    rng = np.random.default_rng(5)
+    for m in (2, 3, 6, 8):
+        E = rng.standard_normal((m, 40))
+        G = E @ E.T
+        c = (D * m)()
+        assert lib.ric_diis_coefficients((D * (m * m))(*G.reshape(-1)), m, c) == 0
+        A = np.zeros((m + 1, m + 1))
+        A[:m, :m] = G
+        A[m, :m] = A[:m, m] = 1.0
+        want = np.linalg.solve(A, np.r_[np.zeros(m), 1.0])[:m]
+        assert np.allclose(list(c), want, rtol=1e-10, atol=1e-12)
+        assert abs(sum(c) - 1.0) < 1e-12
+    G = np.ones((3, 3))            # three identical error vectors: singular
+    c = (D * 3)()
+    assert lib.ric_diis_coefficients((D * 9)(*G.reshape(-1)), 3, c) == 0
+    assert list(c) == [0.0, 0.0, 1.0]
+    assert lib.ric_diis_coefficients((D * 1)(1.0), 0, c) != 0
+
+
+def test_sorted_tuple_rdms_equal_ordered_tuple_rdms():
+    """The spin-free RDM builder over increasing spin-orbital tuples (with the sorting sign) equals
+    the one over every ordered tuple, on dense and sparse CAS vectors."""
+    import synthetic as S
+    rng = np.random.default_rng(9)
+    for na, frac in ((1, 1.0), (3, 1.0), (5, 1.0), (7, 0.1)):
+        d, c = S.random_ci(rng, na, frac)
+        for a, b in zip(S.spinfree_rdms(d, c, na, 3), S.spinfree_rdms_ordered(d, c, na, 3)):
+            assert np.abs(a - b).max() < 1e-14

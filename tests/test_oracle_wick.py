@@ -123,7 +123,7 @@ def test_commutator_matches_fock_space(system, ra, sa, rb, sb):
         ABy = gno.operator_apply({ra: Ta}, By, vid + ("B",))
         BAy = gno.operator_apply({rb: Tb}, Ay, vid + ("A",))
         want = ABy - BAy
-        assert np.abs(got - want).max() < 1e-10 * max(1.0, np.abs(want).max())
+        assert np.abs(got - want).max() < 1e-10 * np.abs(want).max()
     gno._vec_cache.clear()
 
 

@@ -51,6 +51,34 @@ def test_plan_matches_oracle(plan_text, nc, na, nv, naux, seed):
     assert abs(float(tens["E"]) - ref.energy(T1, T2)) < 1e-12
 
 
+@pytest.mark.parametrize("nc,na,nv,naux,seed", [(2, 4, 10, 48, 1), (1, 6, 4, 11, 5), (4, 0, 9, 20, 4)])
+def test_plan_term_groups_match_oracle_groups(plan_text, nc, na, nv, naux, seed):
+    """The plan's residual_lin and residual_quad sections (the term groups ric_residual can select)
+    reproduce the oracle's linear and quadratic groups, and add up to the whole residual."""
+    cfg = S.custom_config("p", nc, na, nv, naux, seed)
+    inp = S.make_inputs(cfg)
+    ref = R.Reference(nc, na, nv, inp.f, inp.B, inp.G1, inp.G2, inp.G3)
+    nH, nP = nc + na, na + nv
+    rng = np.random.default_rng(seed + 50)
+    m1, m2 = R.block_mask(nc, na, nv)
+    T1 = rng.standard_normal((nH, nP)) * 0.05 * m1
+    T2 = rng.standard_normal((nH, nH, nP, nP)) * 0.05
+    T2 = 0.5 * (T2 + T2.transpose(1, 0, 3, 2)) * m2
+    it = Interpreter(plan_text, nc, na, nv, naux)
+    out = {}
+    for sec, grp in (("residual_lin", "lin"), ("residual_quad", "quad"), ("residual", None)):
+        tens = prepare(inp.f, inp.B, inp.G1, inp.G2, inp.G3, nc, na, nv)
+        tens.update(T1=T1, T2=T2, R1=np.zeros((nH, nP)), R2=np.zeros((nH, nH, nP, nP)))
+        it.run(sec, tens)
+        out[sec] = (tens["R1"].copy(), tens["R2"].copy())
+        if grp is not None:
+            r1, r2 = ref.residual(T1, T2, groups=(grp,))
+            assert np.abs(out[sec][0] - r1).max() < 1e-12
+            assert np.abs(out[sec][1] - r2).max() < 1e-12
+    for i in range(2):
+        assert np.abs(out["residual_lin"][i] + out["residual_quad"][i] - out["residual"][i]).max() < 1e-12
+
+
 def test_library_exports_every_declared_symbol():
     if not os.path.exists(LIB):
         pytest.skip("library not built")

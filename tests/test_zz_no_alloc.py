@@ -61,7 +61,7 @@ def test_update_noalloc_matches_update_on_two_calls():
         N1 = R.ric_update(T1, r1, D1, s) * m1
         N2 = R.ric_update(T2, r2, D2, s) * m2
         for got, want in ((b1, N1), (b2, N2)):
-            assert np.abs(got.cpu().numpy() - want).max() <= 1e-14 * max(1.0, np.abs(want).max())
+            assert np.abs(got.cpu().numpy() - want).max() <= 1e-14 * np.abs(want).max()
         want2 = float(np.sum((N1 - T1) ** 2) + np.sum((N2 - T2) ** 2))
         assert abs(nb2 - want2) <= 1e-12 * want2
         ctx.close()
