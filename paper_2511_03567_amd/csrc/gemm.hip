@@ -51,9 +51,12 @@ __device__ inline void mma(f4& c, float a, float b) {
 
 // Geometry of one kernel instance: BM x BN tile, K slab BK, WM x WN wavefronts, each owning
 // TI x TJ MFMA tiles of 16 x 16.
-template <int BM_, int BN_, int BK_, int WM_, int WN_, int MINB_ = 1, int TI_ = 4, int TJ_ = 4>
+// CO: K-major operands are read two rows per thread, consecutive threads on consecutive rows
+// (one coalesced pass per pair of k), instead of a run of rows per thread.
+template <int BM_, int BN_, int BK_, int WM_, int WN_, int MINB_ = 1, int TI_ = 4, int TJ_ = 4, bool CO_ = false>
 struct Geo {
   static constexpr int BM = BM_, BN = BN_, BK = BK_, WM = WM_, WN = WN_, MINB = MINB_, TI = TI_, TJ = TJ_;
+  static constexpr bool CO = CO_;
   static constexpr int NT = 64 * WM * WN;
   static_assert(BM == WM * 16 * TI && BN == WN * 16 * TJ, "wave tiles");
 };
@@ -61,8 +64,8 @@ struct Geo {
 // How the threads of a workgroup load one operand's R x BK slab and where it sits in LDS.
 //  TR = false: rows of K contiguous.  Each thread loads KPT consecutive k of one row.
 //  TR = true:  K-major ([k][row], rows contiguous).  Each thread loads RPT consecutive rows
-//              of one k.
-template <typename T, int R, int BK, int NT, bool TR>
+//              of one k (RPT = one vector when CO).
+template <typename T, int R, int BK, int NT, bool TR, bool CO = false>
 struct Tile {
   static constexpr int VW = 16 / (int)sizeof(T);
   // row-major source
@@ -73,7 +76,7 @@ struct Tile {
   static constexpr int LDSK = BK + 1;
   // K-major source
   static constexpr int RPT0 = R * BK / NT;
-  static constexpr int RPT = RPT0 < VW ? VW : RPT0;   // rows per thread
+  static constexpr int RPT = (CO || RPT0 < VW) ? VW : RPT0;   // rows per thread
   static constexpr int TPK = R / RPT;                 // threads per k
   static constexpr int KPP = NT / TPK;                // k per pass
   static constexpr int PT = (BK + KPP - 1) / KPP;     // passes
@@ -195,8 +198,8 @@ gemm_nt_kernel(int M, int N, int K, double alpha, const T* __restrict__ A, long 
                long strideA, long strideB, long strideC, int zdiv, int ksplit, long strideP,
                double* __restrict__ partial) {
   constexpr int BM = Gm::BM, BN = Gm::BN, BK = Gm::BK, NT = Gm::NT;
-  using TileA = Tile<T, BM, BK, NT, TA>;
-  using TileB = Tile<T, BN, BK, NT, TB>;
+  using TileA = Tile<T, BM, BK, NT, TA, Gm::CO>;
+  using TileB = Tile<T, BN, BK, NT, TB, Gm::CO>;
   __shared__ T As[2][TileA::LDS];
   __shared__ T Bs[2][TileB::LDS];
   const int tid = threadIdx.x;
@@ -355,10 +358,12 @@ hipError_t launch_geo(const GemmArgs& g, const T* A, const T* B, TC* C, hipStrea
   const int tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
   // Split K when there are few tiles, choosing the factor so the workgroups fill whole rounds
   // of the resident slots (256 CUs x 2 workgroups of these geometries): the smallest factor
-  // reaching 95 % of the slots in every round, else the best one found.
+  // reaching 95 % of the slots in every round, else the best one found.  Skinny tiles (one
+  // side 16) stream their operand with little work per byte and may split further.
   int ksplit = 1;
   if (g.K > 0 && sizeof(TC) == sizeof(double)) {
     constexpr long kSlots = 512;
+    constexpr int kMaxSplit = (BM == 16 || BN == 16) ? 512 : 64;
     const long base = (long)tiles * g.batch;
     auto fill = [&](long ks) {
       const long w = base * ks;
@@ -366,7 +371,7 @@ hipError_t launch_geo(const GemmArgs& g, const T* A, const T* B, TC* C, hipStrea
     };
     if (base < 4 * kSlots) {
       double best = fill(1);
-      for (int ks = 2; ks <= 64; ++ks) {
+      for (int ks = 2; ks <= kMaxSplit; ++ks) {
         if ((long)g.K / ks < 512) break;
         if ((size_t)ks * g.batch * g.M * g.N > scratch_elems) break;
         const double e = fill(ks);
@@ -412,6 +417,10 @@ hipError_t launch_geo(const GemmArgs& g, const T* A, const T* B, TC* C, hipStrea
 // best with 64x128x32 tiles at up to three workgroups per CU (8-20 % over 128x128x32 at one)
 using GeoF64 = Geo<128, 128, 16, 2, 2, 2>;
 using GeoF32 = Geo<64, 128, 32, 2, 2, 2, 2, 4>;
+// products with one side of at most 16 (full contractions down to a small active-index
+// block): a 256 x 16 (16 x 256) tile, four waves along the long side, each 64 x 16
+using GeoF64SkinnyN = Geo<256, 16, 16, 4, 1, 2, 4, 1, true>;
+using GeoF64SkinnyM = Geo<16, 256, 16, 1, 4, 2, 1, 4, true>;
 
 template <typename T, typename Acc, typename TC>
 hipError_t launch(const GemmArgs& g, const T* A, const T* B, TC* C, hipStream_t st, double* scratch,
@@ -423,7 +432,11 @@ hipError_t launch(const GemmArgs& g, const T* A, const T* B, TC* C, hipStream_t 
     if constexpr (sizeof(T) == 8) return launch_geo<T, Acc, TC, GeoF64, 1>(g, A, B, C, st, scratch, scratch_elems);
     else return launch_geo<T, Acc, TC, GeoF32, 1>(g, A, B, C, st, scratch, scratch_elems);
   }
-  if constexpr (sizeof(T) == 8) return launch_geo<T, Acc, TC, GeoF64, 0, true>(g, A, B, C, st, scratch, scratch_elems);
+  if constexpr (sizeof(T) == 8) {
+    if (g.N <= 16 && g.M > 16) return launch_geo<T, Acc, TC, GeoF64SkinnyN, 0, true>(g, A, B, C, st, scratch, scratch_elems);
+    if (g.M <= 16 && g.N > 16) return launch_geo<T, Acc, TC, GeoF64SkinnyM, 0, true>(g, A, B, C, st, scratch, scratch_elems);
+    return launch_geo<T, Acc, TC, GeoF64, 0, true>(g, A, B, C, st, scratch, scratch_elems);
+  }
   else return launch_geo<T, Acc, TC, GeoF32, 0, sizeof(TC) == 8>(g, A, B, C, st, scratch, scratch_elems);
 }
 

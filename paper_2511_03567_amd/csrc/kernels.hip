@@ -179,49 +179,95 @@ __device__ inline double phi(double D, double s) {
   return -expm1(-s * D * D) / D;
 }
 
-// Rows of the amplitude arrays: T1 row k (np elements) and T2 row (k, l, c) (np elements over d).
-// Each workgroup takes a contiguous range of rows; the hole part of Delta and the mask are
-// per row, so the inner loop is a coalesced stream over d with no index arithmetic.
+// Position of a wave's lane in the flat [nh][nh][np][np] doubles array: the element's
+// particle index d and its row (k, l, c) with the row's hole part of Delta and its mask.
+struct Amp2Cursor {
+  int k, l, c, d;
+  double dh;
+  bool mrow;
+};
+
+__device__ inline void cursor_row(Amp2Cursor& q, const double* eps, const double* epsP, int nc, int na) {
+  q.dh = eps[q.k] + eps[q.l] - epsP[q.c];
+  q.mrow = q.k >= nc && q.l >= nc && q.c < na;   // T2 all-active left out (with d < na)
+}
+
+// Step the cursor by `by` elements along the flat array (rows advance in (k, l, c) order).
+__device__ inline void cursor_step(Amp2Cursor& q, int by, int nh, int np, const double* eps, const double* epsP,
+                                   int nc, int na) {
+  q.d += by;
+  if (q.d < np) return;
+  while (q.d >= np) {
+    q.d -= np;
+    if (++q.c == np) {
+      q.c = 0;
+      if (++q.l == nh) {
+        q.l = 0;
+        ++q.k;
+      }
+    }
+  }
+  if (q.k < nh) cursor_row(q, eps, epsP, nc, na);
+}
+
+// The regularized update over T1 and T2 with each block's share of sum (t_new - t)^2.
+// T2 is read as one flat stream: each wave takes a contiguous span of it, its 64 lanes on
+// consecutive elements, four elements per lane in flight; a lane's row indices and Delta
+// follow it incrementally, with no division per element.
 __global__ void __launch_bounds__(kThreads)
 update_kernel(double* __restrict__ t1, double* __restrict__ t2, const double* __restrict__ r1,
               const double* __restrict__ r2, const double* __restrict__ eps, int nc, int na, int nv,
               double s, double* __restrict__ partial) {
   const int nh = nc + na, np = na + nv;
-  const long rows = (long)nh + (long)nh * nh * np;
-  const long per = (rows + gridDim.x - 1) / gridDim.x;
-  const long beg = blockIdx.x * per;
-  const long end = beg + per < rows ? beg + per : rows;
   const double* epsP = eps + nc;
   double acc = 0.0;
-  for (long r = beg; r < end; ++r) {
-    double* t;
-    const double* q;
-    double Dh;
-    bool masked;
-    if (r < nh) {
-      const int k = (int)r;
-      t = t1 + (long)k * np;
-      q = r1 + (long)k * np;
-      Dh = eps[k];
-      masked = k >= nc;                  // T1 active -> active left out
-    } else {
-      const long u = r - nh;             // (k, l, c)
-      const int c = (int)(u % np);
-      const long kl = u / np;
-      const int l = (int)(kl % nh), k = (int)(kl / nh);
-      t = t2 + u * np;
-      q = r2 + u * np;
-      Dh = eps[k] + eps[l] - epsP[c];
-      masked = k >= nc && l >= nc && c < na;   // T2 all-active left out
-    }
-    const int dmin = masked ? na : 0;    // the excluded all-active elements lead the row
-    for (int d = dmin + threadIdx.x; d < np; d += blockDim.x) {
-      const double D = Dh - epsP[d];
-      const double tv = t[d];
-      const double nw = (tv * D + q[d]) * phi(D, s);
-      const double dv = nw - tv;
-      acc += dv * dv;
-      t[d] = nw;
+  const long n1 = (long)nh * np;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n1; i += (long)gridDim.x * blockDim.x) {
+    const int k = (int)(i / np), d = (int)(i - (long)k * np);
+    if (k >= nc && d < na) continue;      // T1 active -> active left out
+    const double D = eps[k] - epsP[d];
+    const double tv = t1[i];
+    const double nw = (tv * D + r1[i]) * phi(D, s);
+    const double dv = nw - tv;
+    acc += dv * dv;
+    t1[i] = nw;
+  }
+  constexpr int kU = 4;                    // elements per lane in flight
+  const long n2 = n1 * n1;
+  const int lane = threadIdx.x & 63;
+  const long waves = (long)gridDim.x * (blockDim.x >> 6);
+  const long wid = (long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const long span = ((n2 + waves - 1) / waves + 64 * kU - 1) / (64 * kU) * (64 * kU);
+  const long beg = wid * span, end = beg + span < n2 ? beg + span : n2;
+  if (beg + lane < end) {
+    Amp2Cursor q;
+    amp2_index(beg + lane, nh, np, q.k, q.l, q.c, q.d);
+    cursor_row(q, eps, epsP, nc, na);
+    for (long i = beg + lane; i < end; i += 64 * kU) {
+      long idx[kU];
+      double D[kU], tv[kU], rv[kU];
+      bool on[kU];
+#pragma unroll
+      for (int j = 0; j < kU; ++j) {
+        idx[j] = i + 64L * j;
+        on[j] = idx[j] < end && !(q.mrow && q.d < na);
+        D[j] = q.dh - epsP[q.d < np ? q.d : 0];
+        if (j + 1 < kU) cursor_step(q, 64, nh, np, eps, epsP, nc, na);
+      }
+#pragma unroll
+      for (int j = 0; j < kU; ++j) {
+        tv[j] = on[j] ? t2[idx[j]] : 0.0;
+        rv[j] = on[j] ? r2[idx[j]] : 0.0;
+      }
+#pragma unroll
+      for (int j = 0; j < kU; ++j) {
+        if (!on[j]) continue;
+        const double nw = (tv[j] * D[j] + rv[j]) * phi(D[j], s);
+        const double dv = nw - tv[j];
+        acc += dv * dv;
+        t2[idx[j]] = nw;
+      }
+      cursor_step(q, 64, nh, np, eps, epsP, nc, na);
     }
   }
   acc = block_sum(acc);

@@ -653,16 +653,19 @@ struct ric_ctx {
 
     // K not a multiple of the GEMM's vector width (2 doubles / 4 floats): for large products
     // both operands are gathered into rows of Kp >= K with zero padding so the 16-byte load
-    // path applies (the padding adds zero terms)
+    // path applies (the padding adds zero terms).  Skinny products (an output side of at
+    // most 16) are bound by reading the large operand once: they read it in place with
+    // scalar loads rather than copy it.
     const long vw = use32 ? 4 : 2;
+    const bool skinny = !use32 && std::min(M, N) <= 16;
     long Kp = K;
-    if (K % vw != 0 && flops > pad_min_flops && !aK.empty()) {
+    if (K % vw != 0 && flops > pad_min_flops && !aK.empty() && !skinny) {
       Kp = (K + vw - 1) / vw * vw;
       directA = directB = tA = tB = false;
     }
     // large products keep 16-byte loads: a K-major operand needs its contiguous extent and
     // leading dimension in whole vectors, else it is gathered
-    if (flops > pad_min_flops) {
+    if (flops > pad_min_flops && !skinny) {
       if (tA && (M % vw != 0 || tldA % vw != 0)) tA = false;
       if (tB && (N % vw != 0 || tldB % vw != 0)) tB = false;
     }
