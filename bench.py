@@ -37,7 +37,7 @@ METRIC = "s/residual-iteration & TFLOP/s, 809-orb CAS(12,12); FP32-mixed vs FP64
 # HBM bytes of one ladder call at the 809-orbital shape, from FETCH_SIZE / WRITE_SIZE passes
 # (profiles/ladder_b12_cas1212_hbm_counters.md), scaled by the copy-kernel calibration.  Valid
 # only for the kernel sources they were taken on; any change to them reports null.
-LADDER_TRAFFIC = {"bytes": 7.855e13, "sources_sha256": "c769d0e0305e1d2a", "workload": "b12_cas1212"}
+LADDER_TRAFFIC = {"bytes": 7.8387e13, "sources_sha256": "0c27777072eb9b16", "workload": "b12_cas1212"}
 
 
 def log(msg):

@@ -10,12 +10,16 @@ to rounding.
   dF:  f[p][q] and f[q][p] together, p <= q (every pair);
   dB:  B[X][p][q] and B[X][q][p] together, p <= q: every element at the small shape, a seeded
        sample at the larger one.
-Run from the repository root (uses up to 4 worker processes):
-    python tests/golden/make_adjoint_golden.py
+Run from the repository root (worker processes, one BLAS thread each):
+    python tests/golden/make_adjoint_golden.py [workers]
 """
 import os
 import sys
+import time
 from multiprocessing import Pool
+
+os.environ.setdefault("OMP_NUM_THREADS", "1")
+os.environ.setdefault("OPENBLAS_NUM_THREADS", "1")
 
 import numpy as np
 
@@ -55,11 +59,15 @@ def _init(nc, na, nv, naux, seed):
     cfg, inp, T, x = case_inputs(nc, na, nv, naux, seed)
     _W.update(nc=nc, na=na, nv=nv, inp=inp, T=T, x=x)
     R.term_lists()
+    _W["base"] = R.Reference(nc, na, nv, inp.f, inp.B, inp.G1, inp.G2, inp.G3)
 
 
 def _f(f, B, T1, T2):
     w = _W
-    ref = R.Reference(w["nc"], w["na"], w["nv"], f, B, w["inp"].G1, w["inp"].G2, w["inp"].G3)
+    if f is w["inp"].f and B is w["inp"].B:
+        ref = w["base"]
+    else:
+        ref = R.Reference(w["nc"], w["na"], w["nv"], f, B, w["inp"].G1, w["inp"].G2, w["inp"].G3)
     r1, r2 = ref.residual(T1, T2)
     return float(np.sum(w["x"][0] * r1) + np.sum(w["x"][1] * r2))
 
@@ -93,6 +101,7 @@ def _job(job):
 
 
 def main():
+    workers = int(sys.argv[1]) if len(sys.argv) > 1 else 4
     for nc, na, nv, naux, seed, nsample in SHAPES:
         cfg, inp, T, x = case_inputs(nc, na, nv, naux, seed)
         nH, nP, n = nc + na, na + nv, nc + na + nv
@@ -110,8 +119,13 @@ def main():
         jobs = ([("t1", i) for i in t1_idx] + [("t2", i) for i in t2_idx] + [("f", i) for i in f_idx]
                 + [("b", i) for i in b_idx])
         print(f"shape nc={nc} na={na} nv={nv} naux={naux}: {len(jobs)} directional derivatives", flush=True)
-        with Pool(4, initializer=_init, initargs=(nc, na, nv, naux, seed)) as pool:
-            vals = pool.map(_job, jobs, chunksize=8)
+        t0 = time.perf_counter()
+        vals = []
+        with Pool(workers, initializer=_init, initargs=(nc, na, nv, naux, seed)) as pool:
+            for i, v in enumerate(pool.imap(_job, jobs, chunksize=8)):
+                vals.append(v)
+                if (i + 1) % 500 == 0:
+                    print(f"  {i + 1} done, {time.perf_counter() - t0:.0f} s", flush=True)
         a, b = len(t1_idx), len(t1_idx) + len(t2_idx)
         c = b + len(f_idx)
         out = os.path.join(HERE, f"adjoint_vjp_{nc}_{na}_{nv}_{naux}.npz")
