@@ -328,13 +328,22 @@ class Evaluator:
         return blk
 
     def antisym_eri(self, spaces):
-        """<pq||rs> = (pr|qs) - (ps|qr) over spin orbitals, for one block of spaces (cached)."""
+        """<pq||rs> = (pr|qs) - (ps|qr) over spin orbitals, for one block of spaces (cached).
+
+        Built a slice of p at a time: each library product then has fewer than 2^31 output
+        elements (the limit of 32-bit BLAS indexing), with the same sums over X."""
         key = ("v", spaces)
         if key not in self._cache:
             sp, sq, sr, ss = spaces
             B = lambda a, b: self.block("B", (None, a, b))
-            v = np.einsum("Xpr,Xqs->pqrs", B(sp, sr), B(sq, ss), optimize=True)
-            v -= np.einsum("Xps,Xqr->pqrs", B(sp, ss), B(sq, sr), optimize=True)
+            Bpr, Bqs, Bps, Bqr = B(sp, sr), B(sq, ss), B(sp, ss), B(sq, sr)
+            npp, nq, nr, ns = Bpr.shape[1], Bqs.shape[1], Bpr.shape[2], Bqs.shape[2]
+            v = np.empty((npp, nq, nr, ns))
+            step = max(1, (1 << 28) // max(1, nq * nr * ns))
+            for p0 in range(0, npp, step):
+                sl = slice(p0, p0 + step)
+                v[sl] = np.einsum("Xpr,Xqs->pqrs", Bpr[:, sl], Bqs, optimize=True)
+                v[sl] -= np.einsum("Xps,Xqr->pqrs", Bps[:, sl], Bqr, optimize=True)
             self._cache[key] = v
         return self._cache[key]
 
