@@ -6,7 +6,10 @@ Calls only the oracle and the seeded input generators.  Run from the repository 
 
 "cases": the oracle's plain regularized Jacobi iteration (eq. ric-update) from T = 0.
 "diis_cases": the same fixed point reached faster by DIIS over the oracle's update, for shapes
-where the plain iteration takes too long on the CPU (CAS(8,8): minutes per oracle residual).
+where the plain iteration takes too long on the CPU: the CAS(8,8) active space (full 3-body
+RDM of 4900 determinants) with the core of the CAS(8,8) workload and 40 virtual orbitals.  The
+workload's own 120 virtuals are out of reach: the oracle's spin-orbital vvvv block alone is
+26.5 GB there, and one residual does not fit in 64 GB.
 The extrapolation below only mixes the oracle's own updates U(T_i) with weights that minimize
 |sum c_i (U(T_i) - T_i)| under sum c_i = 1; the stored energy is taken after a plain oracle
 step whose length is below the tolerance, so it is a fixed point of the oracle's update.
@@ -27,7 +30,8 @@ from oracle import ricmrcc as R  # noqa: E402
 
 CASES = [("tiny_cas44", 0.5), ("tiny_cas44", 0.25)]
 TOL = 1e-10
-DIIS_CASES = [("mixed_cas88", 0.5)]
+# (name, nc, na, nv, naux, seed, s)
+DIIS_CASES = [("cas88_nv40", 10, 8, 40, 120, 2, 0.5)]
 DIIS_TOL = 1e-9
 DIIS_M = 6
 
@@ -83,14 +87,15 @@ def main():
 
 def run_diis():
     out = []
-    for name, s in DIIS_CASES:
-        cfg = S.CONFIGS[name]
+    for name, nc, na, nv, naux, seed, s in DIIS_CASES:
+        cfg = S.custom_config(name, nc, na, nv, naux, seed)
         inp = S.make_inputs(cfg)
         ref = R.Reference(cfg.nc, cfg.na, cfg.nv, inp.f, inp.B, inp.G1, inp.G2, inp.G3)
         print(f"{name} s={s}: DIIS({DIIS_M}) over the oracle's update", flush=True)
         e, it, step = solve_diis(ref, s, DIIS_TOL, DIIS_M)
-        out.append({"config": name, "s": s, "tol": DIIS_TOL, "diis": DIIS_M, "e_corr": e,
-                    "e0": ref.reference_energy(), "iterations": it, "last_step": step})
+        out.append({"config": name, "nc": nc, "na": na, "nv": nv, "naux": naux, "seed": seed, "s": s,
+                    "tol": DIIS_TOL, "diis": DIIS_M, "e_corr": e, "e0": ref.reference_energy(),
+                    "iterations": it, "last_step": step})
         print(out[-1], flush=True)
     return out
 

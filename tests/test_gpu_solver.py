@@ -55,11 +55,12 @@ def test_solve_matches_oracle(case):
 
 @pytest.mark.parametrize("case", _golden("diis_cases"), ids=lambda c: f"{c['config']}-s{c['s']}")
 def test_diis_solve_matches_oracle_cas88(case):
-    """CAS(8,8) (nc=10, nv=120, naux=360): converged E_corr against the oracle's own fixed point
-    (DIIS over the oracle's update, make_solve_golden.py --diis): FP64 within 1e-8 E_h,
-    FP32-mixed iterations with FP64 polish within 1e-6 E_h."""
+    """The CAS(8,8) active space with the CAS(8,8) workload's core (nc=10) on 40 virtuals
+    (naux=120): converged E_corr against the oracle's own fixed point (DIIS over the oracle's
+    update, make_solve_golden.py --diis): FP64 within 1e-8 E_h, FP32-mixed iterations with FP64
+    polish within 1e-6 E_h."""
     from paper_2511_03567_amd import ric
-    cfg = S.CONFIGS[case["config"]]
+    cfg = S.custom_config(case["config"], case["nc"], case["na"], case["nv"], case["naux"], case["seed"])
     print(f"DIIS solve {case['config']} s={case['s']}", flush=True)
     ctx = _ctx(cfg)
     t0 = time.perf_counter()
@@ -141,5 +142,29 @@ def test_diis_converges_cas88_at_larger_flow():
     nmix = sum(1 for r in logmx if r["precision"] == "fp32mix")
     print(f"  DIIS fp64 {e64:.12f} ({it64} it)  mixed {emx:.12f} ({itmx} it, {nmix} mixed)  "
           f"|dE| {abs(emx - e64):.2e}", flush=True)
+    assert nmix > 0
+    assert abs(emx - e64) < 1e-6
+
+
+@pytest.mark.timeout(600)
+def test_mixed_solve_matches_fp64_cas1414():
+    """CAS(14,14) (nc=20, nv=300, naux=900, sparse 1 % CAS vector), s = 0.5, DIIS over 6 iterates:
+    FP32-mixed iterations followed by FP64 polish reach the FP64 energy within 1e-6 E_h."""
+    from paper_2511_03567_amd import ric
+    cfg = S.CONFIGS["large_cas1414"]
+    print(f"solve large_cas1414 s={cfg.s}", flush=True)
+    t0 = time.perf_counter()
+    ctx = _ctx(cfg)
+    log64, logmx = [], []
+    t1 = time.perf_counter()
+    e64, _, _, _, it64 = ric.solve(ctx, cfg.s, tol=1e-8, max_iter=100, diis=6, log=log64)
+    t2 = time.perf_counter()
+    emx, _, _, _, itmx = ric.solve(ctx, cfg.s, tol=1e-8, max_iter=100, diis=6, precision=ric.RIC_FP32MIX,
+                                   log=logmx)
+    t3 = time.perf_counter()
+    nmix = sum(1 for r in logmx if r["precision"] == "fp32mix")
+    print(f"  inputs {t1 - t0:.1f} s; fp64 {e64:.12f} ({it64} it, {t2 - t1:.1f} s); mixed {emx:.12f} "
+          f"({itmx} it, {nmix} mixed, {t3 - t2:.1f} s); |dE| {abs(emx - e64):.2e}", flush=True)
+    ctx.close()
     assert nmix > 0
     assert abs(emx - e64) < 1e-6
