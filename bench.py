@@ -37,6 +37,10 @@ METRIC = "s/residual-iteration & TFLOP/s, 809-orb CAS(12,12); FP32-mixed vs FP64
 # HBM bytes of one ladder call at the 809-orbital shape, from FETCH_SIZE / WRITE_SIZE passes
 # (profiles/ladder_b12_cas1212_hbm_counters.md), scaled by the copy-kernel calibration.  Valid
 # only for the kernel sources they were taken on; any change to them reports null.
+# flops of one residual at the 809-orbital shape held fixed (the plan's executed count before
+# operand pre-combination), so that TFLOP/s against it follows s/iteration as the plan changes
+FIXED_FLOPS = {"b12_cas1212": 4.397209499209308e15}
+
 LADDER_TRAFFIC = {"bytes": 7.8387e13, "sources_sha256": "0c27777072eb9b16", "workload": "b12_cas1212"}
 
 
@@ -360,6 +364,8 @@ def main():
         "residual_s": res_s,
         "tflops": flops / dt / 1e12,
         "plan_flops": flops,
+        "tflops_vs_fixed_count": (FIXED_FLOPS[args.config] / dt / 1e12) if args.config in FIXED_FLOPS else None,
+        "fixed_flops": FIXED_FLOPS.get(args.config),
         "roofline": {"bound": "mfma",
                      "kernel": "particle-particle ladder (gemm_nt_kernel<double,...,Site=1> W build and +/- products, "
                                "pack_tau/pack_w/ladder_scatter_pm, splitk_reduce<1>)",

@@ -123,10 +123,12 @@ struct Slot {
   std::string name;
   std::vector<Rng> decl;
   double* ptr = nullptr;
+  const float* ptr32 = nullptr;   // FP32 copy for the mixed path, same layout (or null)
 };
 
 struct View {
   double* p = nullptr;
+  const float* p32 = nullptr;     // the same elements in the slot's FP32 copy, if it has one
   int nd = 0;
   long ext[kMaxDims];
   long str[kMaxDims];
@@ -267,10 +269,22 @@ struct ric_ctx {
   double* noalloc = nullptr;  // this device's copy of `scratch` (set by ric_create)
   const double* Bp = nullptr;  // the loaded DF factors: the owned copy B, or the caller's array (borrowed)
   bool accumulate_theta = false;  // adjoint (f, B) parts added to dF, dB instead of overwriting them
+  // elements of W' per ladder chunk: six c rows at 809 orbitals for the forward residual; the
+  // adjoint sections, whose intermediates take most of the device, keep three
+  static constexpr double kLadderBudgetForward = 2.8e9, kLadderBudgetAdjoint = 1.4e9;
+  double ladder_budget = kLadderBudgetAdjoint;
+  void use_ladder_budget(double b) {
+    if (b < ladder_budget) {   // return the larger chunk buffers before sections that need the room
+      wbuf.release();
+      wbuf2.release();
+    }
+    ladder_budget = b;
+  }
 
   ~ric_ctx() {
     for (DevBuf* b : {&f, &eps, &B, &BT, &BT32, &g1, &g2, &g3, &ga, &ea, &l2, &k2, &l3, &k3, &I4, &I3, &IJ, &IK,
-                      &tau, &Edev, &red, &e0, &scrA, &scrB, &scrC, &scrC2, &scrK, &wbuf, &wbuf2, &lad32, &dfa, &dfb, &dfz, &lgx, &lgt, &lgb, &xr1, &xl})
+                      &tau, &Edev, &red, &e0, &scrA, &scrB, &scrC, &scrC2, &scrK, &wbuf, &wbuf2, &lad32, &dfa, &dfb, &dfz, &lgx, &lgt, &lgb, &xr1, &xl,
+                      &sh_t1, &sh_t2, &sh_b, &sh_i4, &sh_i3, &sh_ij, &sh_ik})
       b->release();
     pool.release();
     if (solver) (void)rocblas_destroy_handle(solver);
@@ -463,7 +477,54 @@ struct ric_ctx {
       off += sz.off(s.decl[i], o.sub[i]) * full[i];
     }
     v.p = empty ? nullptr : s.ptr + off;
+    v.p32 = (empty || !s.ptr32) ? nullptr : s.ptr32 + off;
     return v;
+  }
+
+  // -- FP32 copies of stored operands for the mixed path ----------------------------------------
+  // The amplitudes are copied at each mixed residual; the DF factors and the stored integral
+  // blocks once after each ric_load_df.  Large FP32 products read these in place instead of
+  // converting their operands product by product.
+  DevBuf sh_t1, sh_t2, sh_b, sh_i4, sh_i3, sh_ij, sh_ik;
+  bool shadows_static = false;
+
+  void make_shadow(const char* name, DevBuf& buf) {
+    const int id = slot_of.at(name);
+    Slot& s = slots[id];
+    s.ptr32 = nullptr;
+    const long n = slot_elems(id);
+    if (!s.ptr || n == 0) return;
+    buf.ensure(((size_t)n + 1) / 2);
+    View v;
+    v.p = s.ptr;
+    v.nd = (int)s.decl.size();
+    long st = 1;
+    for (int i = v.nd - 1; i >= 0; --i) {
+      v.ext[i] = sz.ext(s.decl[i]);
+      v.str[i] = st;
+      v.lab[i] = i;
+      st *= v.ext[i];
+    }
+    std::vector<int> ord(v.nd);
+    for (int i = 0; i < v.nd; ++i) ord[i] = i;
+    gather(v, ord, nullptr, reinterpret_cast<float*>(buf.p));
+    s.ptr32 = reinterpret_cast<const float*>(buf.p);
+  }
+
+  void static_shadows() {
+    if (shadows_static) return;
+    make_shadow("B", sh_b);
+    make_shadow("I4", sh_i4);
+    make_shadow("I3", sh_i3);
+    make_shadow("IJ", sh_ij);
+    make_shadow("IK", sh_ik);
+    shadows_static = true;
+  }
+
+  void drop_shadows() {
+    for (const char* nm : {"B", "I4", "I3", "IJ", "IK", "T1", "T2"}) slots[slot_of.at(nm)].ptr32 = nullptr;
+    for (DevBuf* b : {&sh_b, &sh_i4, &sh_i3, &sh_ij, &sh_ik, &sh_t1, &sh_t2}) b->release();
+    shadows_static = false;
   }
 
   long slot_elems(int id) {
@@ -621,8 +682,10 @@ struct ric_ctx {
     ordA.insert(ordA.end(), aK.begin(), aK.end());
     ordB.insert(ordB.end(), bK.begin(), bK.end());
     long sAm, sAk, sBn, sBk;
-    bool directA = !use32 && mergeable(a, aM, sAm) && mergeable(a, aK, sAk) && sAk == 1;
-    bool directB = !use32 && mergeable(b, bN, sBn) && mergeable(b, bK, sBk) && sBk == 1;
+    // in mixed precision an operand is read in place only from its FP32 copy
+    const bool inA = !use32 || a.p32 != nullptr, inB = !use32 || b.p32 != nullptr;
+    bool directA = inA && mergeable(a, aM, sAm) && mergeable(a, aK, sAk) && sAk == 1;
+    bool directB = inB && mergeable(b, bN, sBn) && mergeable(b, bK, sBk) && sBk == 1;
     if (directA && M > 1 && sAm < K) directA = false;
     if (directB && N > 1 && sBn < K) directB = false;
     if (M == 1) sAm = K;
@@ -631,14 +694,14 @@ struct ric_ctx {
     // K-major in place
     bool tA = false, tB = false;
     long tldA = 0, tldB = 0;
-    if (!use32 && !directA && M > 1 && K > 1) {
+    if (inA && !directA && M > 1 && K > 1) {
       long sm, sk;
       if (mergeable(a, aM, sm) && sm == 1 && mergeable(a, aK, sk) && sk >= M) {
         tA = true;
         tldA = sk;
       }
     }
-    if (!use32 && !directB && N > 1 && K > 1) {
+    if (inB && !directB && N > 1 && K > 1) {
       long sn, sk;
       if (mergeable(b, bN, sn) && sn == 1 && mergeable(b, bK, sk) && sk >= N) {
         tB = true;
@@ -671,8 +734,8 @@ struct ric_ctx {
     }
     if (!directA && !tA) scrA.ensure(use32 ? ((size_t)M * Kp + 1) / 2 : (size_t)M * Kp);
     if (!directB && !tB) scrB.ensure(use32 ? ((size_t)N * Kp + 1) / 2 : (size_t)N * Kp);
-    const double* pA = a.p;
-    const double* pB = b.p;
+    const double* pA = use32 ? reinterpret_cast<const double*>(a.p32) : a.p;
+    const double* pB = use32 ? reinterpret_cast<const double*>(b.p32) : b.p;
     if (tA) sAm = tldA;
     if (tB) sBn = tldB;
     if (!directA && !tA) {
@@ -823,10 +886,12 @@ struct ric_ctx {
         return;
       }
     }
-    // L2 as [(q,s)][X]
+    // L2 as [(q,s)][X]; in mixed precision the block is built from FP32 copies of the factors
+    // (FP32 tiles, FP64 carry per K slab, FP64 block) like the other large products
+    const bool use32 = precision == RIC_FP32MIX && 2.0 * (double)nx * np_ * nr * nq * ns > fp32_min_flops;
     DevBuf& l2buf = dfb;
-    l2buf.ensure((size_t)nq * ns * nx);
-    gather(L2, {1, 2, 0}, l2buf.p, nullptr);
+    l2buf.ensure(use32 ? ((size_t)nq * ns * nx + 1) / 2 : (size_t)nq * ns * nx);
+    gather(L2, {1, 2, 0}, use32 ? nullptr : l2buf.p, use32 ? reinterpret_cast<float*>(l2buf.p) : nullptr);
     const long per = std::max<long>(1, (long)(1.2e9 / std::max<long>(1, nr * nq * ns)));
     const long chunk = std::min(np_, per);
     const int lp = L1.lab[1];
@@ -835,8 +900,8 @@ struct ric_ctx {
       View l1c = L1;
       l1c.p += p0 * L1.str[1];
       l1c.ext[1] = pc;
-      dfa.ensure((size_t)pc * nr * nx);
-      gather(l1c, {1, 2, 0}, dfa.p, nullptr);
+      dfa.ensure(use32 ? ((size_t)pc * nr * nx + 1) / 2 : (size_t)pc * nr * nx);
+      gather(l1c, {1, 2, 0}, use32 ? nullptr : dfa.p, use32 ? reinterpret_cast<float*>(dfa.p) : nullptr);
       wbuf.ensure((size_t)pc * nr * nq * ns);
       GemmArgs g;
       g.M = (int)(pc * nr);
@@ -847,7 +912,11 @@ struct ric_ctx {
       g.C = wbuf.p;
       g.ldc = nq * ns;
       scrK.ensure(kSplitScratch);
-      HIPCHK(ric::gemm_nt_f64(g, dfa.p, l2buf.p, stream, scrK.p, scrK.n));
+      if (use32)
+        HIPCHK(ric::gemm_nt_f32(g, reinterpret_cast<const float*>(dfa.p), reinterpret_cast<const float*>(l2buf.p),
+                                stream, scrK.p, scrK.n));
+      else
+        HIPCHK(ric::gemm_nt_f64(g, dfa.p, l2buf.p, stream, scrK.p, scrK.n));
       View e;
       e.p = wbuf.p;
       e.nd = 4;
@@ -902,7 +971,7 @@ struct ric_ctx {
     else HIPCHK(ric::pack_tau(taup, nh, np_, tpd, tmd, ldp, ldm, stream));
     // chunk of c rows: W'[(c,e)][(d,f)] (one GEMM), then W+/- per (c,d) pair
     // elements of W' per chunk (RIC_LADDER_BUDGET overrides)
-    const double budget = getenv("RIC_LADDER_BUDGET") ? std::atof(getenv("RIC_LADDER_BUDGET")) : 1.4e9;
+    const double budget = getenv("RIC_LADDER_BUDGET") ? std::atof(getenv("RIC_LADDER_BUDGET")) : ladder_budget;
     long chunk = std::max<long>(1, (long)(budget / ((double)np_ * pp)));
     chunk = std::min<long>(chunk, np_);
     const size_t wel = (size_t)chunk * np_ * pp;
@@ -1391,6 +1460,7 @@ int ric_set_spaces(ric_ctx* ctx, int nc, int na, int nv, int naux) {
       throw Err(RIC_E_ARG, "invalid orbital space sizes");
     ctx->sz = Sizes{nc, na, nv, naux};
     ctx->Bp = nullptr;
+    ctx->drop_shadows();
     ctx->spaces = true;
     ctx->have_f = ctx->have_B = ctx->have_rdm = false;
   });
@@ -1416,6 +1486,7 @@ int ric_load_df(ric_ctx* ctx, const double* B, int borrow) {
     if (!B) throw Err(RIC_E_ARG, "null DF factors");
     const Sizes& s = ctx->sz;
     const long n = s.ext(RG), nx = s.naux, nc = s.nc, np_ = s.ext(RP);
+    ctx->drop_shadows();
     if (borrow) {
       ctx->B.release();   // the caller's array is used in place and must outlive its use here
       ctx->Bp = B;
@@ -1512,13 +1583,23 @@ int ric_residual(ric_ctx* ctx, const double* T1, const double* T2, double* R1, d
       throw Err(RIC_E_ARG, "term mask selects no terms");
     const char* sec = lin && quad ? "residual" : lin ? "residual_lin" : "residual_quad";
     ctx->precision = precision;
+    ctx->use_ladder_budget(ric_ctx::kLadderBudgetForward);
     ctx->bind("T1", T1);
     ctx->bind("T2", T2);
     ctx->bind("R1", R1);
     ctx->bind("R2", R2);
     ctx->ladder_ran = false;
     HIPCHK(hipEventRecord(ctx->ev[2], ctx->stream));
+    if (precision == RIC_FP32MIX) {
+      // FP32 copies of the operands large products read in place: the stored blocks once per
+      // load, the amplitudes at every call (inside the timed region)
+      ctx->static_shadows();
+      ctx->make_shadow("T1", ctx->sh_t1);
+      ctx->make_shadow("T2", ctx->sh_t2);
+    }
     ctx->run(ctx->sections.at(sec), term_mask);
+    ctx->slots[ctx->slot_of.at("T1")].ptr32 = nullptr;
+    ctx->slots[ctx->slot_of.at("T2")].ptr32 = nullptr;
     HIPCHK(hipEventRecord(ctx->ev[3], ctx->stream));
     HIPCHK(hipEventSynchronize(ctx->ev[3]));
     float ms = 0.f;
@@ -1603,6 +1684,7 @@ int ric_ladder(ric_ctx* ctx, const double* tau, double* R2, int precision) {
     if (!tau || !R2) throw Err(RIC_E_ARG, "null pointer");
     if (precision != RIC_FP64 && precision != RIC_FP32MIX) throw Err(RIC_E_ARG, "bad precision");
     ctx->precision = precision;
+    ctx->use_ladder_budget(ric_ctx::kLadderBudgetForward);
     HIPCHK(hipEventRecord(ctx->ev[0], ctx->stream));
     ctx->ladder(tau, R2);
     HIPCHK(hipEventRecord(ctx->ev[1], ctx->stream));
@@ -1623,6 +1705,8 @@ int ric_adjoint_residual(ric_ctx* ctx, const double* T1, const double* T2, const
     const long nh = ctx->sz.nc + ctx->sz.na, np_ = ctx->sz.na + ctx->sz.nv;
     const long n1 = nh * np_, n2 = n1 * n1;
     ctx->precision = RIC_FP64;
+    ctx->use_ladder_budget(ric_ctx::kLadderBudgetAdjoint);
+    ctx->drop_shadows();   // the FP32 operand copies of the mixed path are not needed here
     // cotangents of the masked residuals: R1 as given, R2 through its pair-symmetric part
     ctx->xr1.ensure(n1);
     ctx->xl.ensure(n2);
@@ -1660,6 +1744,8 @@ int ric_energy_gradient(ric_ctx* ctx, const double* T1, const double* T2, double
     ctx->require_loaded();
     if (!T1 || !T2 || !dT1 || !dT2 || !dF || !dB) throw Err(RIC_E_ARG, "null pointer");
     ctx->precision = RIC_FP64;
+    ctx->use_ladder_budget(ric_ctx::kLadderBudgetAdjoint);
+    ctx->drop_shadows();   // the FP32 operand copies of the mixed path are not needed here
     ctx->bind("T1", T1);
     ctx->bind("T2", T2);
     ctx->bind("dT1", dT1);

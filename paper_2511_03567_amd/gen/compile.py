@@ -588,6 +588,8 @@ def _emit_into(plan, coef, ops, out, rng):
 
 
 ACC_CAP = 2.5e9   # elements (cost-model size) above which a group accumulator is chunked
+PRECOMBINE = True  # sum permuted views of a stored operand before the product they share
+SUM_FLOP_PER_BYTE = 20.0  # flops a product must save per byte the summation of its operands moves
 
 
 def _vol(ranges):
@@ -629,6 +631,181 @@ def _tight_ranges(members):
         for l, role in renm.items():
             tight[role] = tight.get(role, 0) | rngm[l]
     return tight
+
+
+
+def _stored(o):
+    """An operand that holds a stored tensor (not an intermediate of this plan, not a DF term)."""
+    return not (o.name in ("?", "ERI") or (o.name.startswith("t") and o.name[1:].isdigit()))
+
+
+def _canon(op, out_labels, own=None):
+    """Labels of op named relative to the output: output label i -> 'o<i>'; a summed label by
+    its order of appearance in the operand that defines `own` (created here when None)."""
+    pos = {l: i for i, l in enumerate(out_labels)}
+    make = own is None
+    own = {} if make else own
+    c = []
+    for l in op.labels:
+        if l in pos:
+            c.append(f"o{pos[l]}")
+        else:
+            if l not in own:
+                if not make:
+                    return None, own
+                own[l] = f"s{len(own)}"
+            c.append(own[l])
+    return tuple(c), own
+
+
+def _sum_views(plan, terms, names, ranges):
+    """A new intermediate sum c * view over terms (c, operand, {canonical name: label}), with its
+    labels in canonical order `names` over `ranges`."""
+    tmp = plan.new_tmp(ranges)
+    plan.lines.append(f"ZERO {tmp}")
+    for c, op, inv in terms:
+        plan.add(Operand(tmp, ranges, [inv[n] for n in names]), c, op)
+    return tmp
+
+
+def _emit_summed_products(plan, items):
+    """out += coef * a . b for items (coef, out, a, b) of stored a, b and one output.
+
+    Products that share one operand (the same stored tensor in the same pattern relative to
+    the output) are emitted once, the other operands (views of one stored tensor) summed
+    first.  When the partner sums of all groups are proportional (after matching their summed
+    labels), the shared operands are summed too and one product remains:
+    sum_g lam_g X_g . P = (sum_g lam_g X_g) . P."""
+    best = None
+    for side in (0, 1):
+        groups = OrderedDict()
+        ok = True
+        for coef, out, a, b in items:
+            X, Z = (a, b) if side == 0 else (b, a)
+            cx, own = _canon(X, out.labels)
+            cz, _ = _canon(Z, out.labels, own)
+            if cz is None:
+                ok = False
+                break
+            key = (X.name, cx, X.ranges, out.ranges, Z.name, tuple(sorted(cz)))
+            g = groups.setdefault(key, OrderedDict())
+            zk = (cz, Z.ranges)
+            if zk in g:
+                g[zk][0] += coef
+                g[zk][2].append((coef, out, a, b))
+            else:
+                g[zk] = [coef, (out, X, Z, own), [(coef, out, a, b)]]
+        if ok and (best is None or len(groups) < len(best[1])):
+            best = (side, groups)
+    if best is None or len(best[1]) == len(items):
+        for coef, out, a, b in items:
+            plan.contract(out, coef, a, b)
+        return
+    groups = [(k, g) for k, g in best[1].items() if any(v[0] != 0 for v in g.values())]
+
+    def product_flops(out, X, Z):
+        rng = {}
+        for o in (out, X, Z):
+            for l, r in zip(o.labels, o.ranges):
+                rng[l] = r
+        f = 2.0
+        for r in rng.values():
+            f *= extent(r)
+        return f
+
+    def worth(saved_flops, sums):
+        """A sum of n views of size s moves (24 n + 8) s bytes (zero, then read each view and
+        read-modify-write the sum); it pays when the products it saves take longer."""
+        moved = sum((24.0 * n + 8.0) * size for n, size in sums)
+        return saved_flops > SUM_FLOP_PER_BYTE * moved
+
+    def inverse(out, own):
+        inv = {f"o{i}": l for i, l in enumerate(out.labels)}
+        inv.update({n: l for l, n in own.items()})
+        return inv
+
+    def partner_sum(g, rename):
+        """Intermediate sum of a group's partners; returns (tmp, names, ranges) with names in the
+        renamed canonical naming."""
+        zks = list(g.keys())
+        names = sorted(rename.get(n, n) for n in zks[0][0])
+        rmap = {rename.get(n, n): r for n, r in zip(zks[0][0], zks[0][1])}
+        ranges = [rmap[n] for n in names]
+        terms = []
+        for zk in zks:
+            c, (out, X, Z, own) = g[zk][:2]
+            inv = inverse(out, own)
+            back = {rename.get(n, n): inv[n] for n in inv}
+            terms.append((c, Z, back))
+        return _sum_views(plan, terms, names, ranges), names, ranges
+
+    # proportional partner sums: match each group's summed-label names to the first group's
+    merge = None
+    if len(groups) > 1 and len({(k[0], tuple(sorted(k[1])), k[3], k[4]) for k, _ in groups}) == 1:
+        k0, g0 = groups[0]
+        base = {zk: v[0] for zk, v in g0.items()}
+        snames = sorted(n for n in k0[1] if n.startswith("s"))
+        merge = [(k0, g0, {}, 1.0)]
+        for k, g in groups[1:]:
+            found = None
+            for perm in itertools.permutations(snames):
+                rn = dict(zip(snames, perm))
+                mapped = {}
+                for (cz, zr), v in g.items():
+                    mapped[(tuple(rn.get(n, n) for n in cz), zr)] = v[0]
+                if set(mapped) != set(base):
+                    continue
+                j = next(zk for zk in base if base[zk] != 0)
+                lam = mapped[j] / base[j]
+                if all(abs(mapped[zk] - lam * base[zk]) <= 1e-12 * max(1.0, abs(mapped[zk])) for zk in base):
+                    xr0 = dict(zip(k0[1], k0[2]))
+                    xr = {rn.get(n, n): r for n, r in zip(k[1], k[2])}
+                    if xr == xr0:
+                        found = (rn, lam)
+                        break
+            if found is None:
+                merge = None
+                break
+            merge.append((k, g, found[0], found[1]))
+    if merge is not None:
+        k0, g0 = groups[0]
+        out0, X0, Z0, own0 = next(iter(g0.values()))[1]
+        nprod = sum(len(g) for _, g in groups)
+        if not worth((nprod - 1) * product_flops(out0, X0, Z0), [(len(merge), X0.size()), (len(g0), Z0.size())]):
+            merge = None
+    if merge is not None:
+        k0, g0 = groups[0]
+        xnames = sorted(k0[1])
+        xrm = dict(zip(k0[1], k0[2]))
+        xr = [xrm[n] for n in xnames]
+        xterms = []
+        for k, g, rn, lam in merge:
+            out, X, Z, own = next(iter(g.values()))[1]
+            inv = inverse(out, own)
+            back = {rn.get(n, n): inv[n] for n in inv}
+            xterms.append((lam, X, back))
+        xt = _sum_views(plan, xterms, xnames, xr)
+        zt, znames, zr = partner_sum(g0, {})
+        out0, X0, Z0, own0 = next(iter(g0.values()))[1]
+        inv0 = inverse(out0, own0)
+        plan.contract(out0, 1, Operand(xt, xr, [inv0[n] for n in xnames]), Operand(zt, zr, [inv0[n] for n in znames]))
+        plan.free(zt)
+        plan.free(xt)
+        return
+    for k, g in groups:
+        zks = list(g.keys())
+        out0, X0, Z0, own0 = g[zks[0]][1]
+        if len(zks) == 1 or not worth((len(zks) - 1) * product_flops(out0, X0, Z0), [(len(zks), Z0.size())]):
+            # the products as they were, each with its own output labels and operand order
+            for zk in zks:
+                for c, out, a, b in g[zk][2]:
+                    plan.contract(out, c, a, b)
+            continue
+        zt, znames, zr = partner_sum(g, {})
+        out0, X0, Z0, own0 = g[zks[0]][1]
+        inv0 = inverse(out0, own0)
+        plan.contract(out0, 1, X0, Operand(zt, zr, [inv0[n] for n in znames]))
+        plan.free(zt)
 
 
 def _emit_groups(plan, groups):
@@ -708,26 +885,38 @@ def _emit_groups(plan, groups):
             zpos = {l: i for i, l in enumerate(zl0)}
             zacc = plan.new_tmp(zr)
             plan.lines.append(f"ZERO {zacc}")
+            single = []
             for coef, X, Z, zlabs, rng, ylabs, m, prefix in items:
                 zop = Operand(zacc, [rng[l] for l in zlabs], zlabs)
-                if prefix:
+                if prefix and len(prefix) == 1 and chunk is None and PRECOMBINE and \
+                        _stored(prefix[0][0]) and _stored(prefix[0][1]):
+                    single.append((coef, zop, prefix[0][0], prefix[0][1]))
+                elif prefix:
                     _emit_steps(plan, prefix, final_out=zop, alpha=coef)
                 else:
                     plan.add(zop, coef, Z)
+            if single:
+                _emit_summed_products(plan, single)
             # X over the ranges of the first member, its inner labels over Z's ranges
             xr = [(zr[zpos[l]] if (l in zl0 and l not in yl0) else r) for l, r in zip(X0.labels, X0.ranges)]
             Xop = Operand(X0.name, xr, X0.labels)
             accop = Operand(acc, [(rng0_[l] if l in X0.labels else zr[zpos[l]]) for l in yl0], yl0)
             plan.contract(accop, 1, Xop, Operand(zacc, zr, zl0))
             plan.free(zacc)
+        single = []
         for coef, ysteps, Yop, ylabs, P0m, ext, out_ranges, rng, ren, g in rest_members:
             # the member's own (possibly narrower) ranges address a sub-block of acc
             ylabs = order(ylabs, ren)
             accop = Operand(acc, [rng[l] for l in ylabs], ylabs)
             if not ysteps:
                 plan.add(accop, coef, Yop)
+            elif len(ysteps) == 1 and chunk is None and PRECOMBINE and _stored(ysteps[0][0]) and \
+                    _stored(ysteps[0][1]):
+                single.append((coef, accop, ysteps[0][0], ysteps[0][1]))
             else:
                 _emit_steps(plan, ysteps, final_out=accop, alpha=coef)
+        if single:
+            _emit_summed_products(plan, single)
         out = Operand(target, [g0[l] for l in ext0], ext0)
         P0 = Operand(P00.name, [g0[l] for l in P00.labels], P00.labels)
         plan.contract(out, 1, P0, Operand(acc, yr, ylabs0))
