@@ -488,13 +488,26 @@ struct ric_ctx {
   DevBuf sh_t1, sh_t2, sh_b, sh_i4, sh_i3, sh_ij, sh_ik;
   bool shadows_static = false;
 
+  // A copy is made only while at least kShadowReserve bytes of the device stay free; an operand
+  // without one is converted product by product as before.
+  static constexpr size_t kShadowReserve = 16UL << 30;
+
   void make_shadow(const char* name, DevBuf& buf) {
     const int id = slot_of.at(name);
     Slot& s = slots[id];
     s.ptr32 = nullptr;
     const long n = slot_elems(id);
     if (!s.ptr || n == 0) return;
-    buf.ensure(((size_t)n + 1) / 2);
+    const size_t need = ((size_t)n + 1) / 2;
+    if (buf.n < need) {
+      size_t free_b = 0, total_b = 0;
+      HIPCHK(hipMemGetInfo(&free_b, &total_b));
+      if (free_b + buf.n * sizeof(double) < need * sizeof(double) + kShadowReserve) {
+        buf.release();
+        return;
+      }
+    }
+    buf.ensure(need);
     View v;
     v.p = s.ptr;
     v.nd = (int)s.decl.size();
@@ -513,11 +526,11 @@ struct ric_ctx {
 
   void static_shadows() {
     if (shadows_static) return;
-    make_shadow("B", sh_b);
-    make_shadow("I4", sh_i4);
-    make_shadow("I3", sh_i3);
-    make_shadow("IJ", sh_ij);
     make_shadow("IK", sh_ik);
+    make_shadow("IJ", sh_ij);
+    make_shadow("B", sh_b);
+    make_shadow("I3", sh_i3);
+    make_shadow("I4", sh_i4);
     shadows_static = true;
   }
 
@@ -1591,11 +1604,17 @@ int ric_residual(ric_ctx* ctx, const double* T1, const double* T2, double* R1, d
     ctx->ladder_ran = false;
     HIPCHK(hipEventRecord(ctx->ev[2], ctx->stream));
     if (precision == RIC_FP32MIX) {
-      // FP32 copies of the operands large products read in place: the stored blocks once per
-      // load, the amplitudes at every call (inside the timed region)
-      ctx->static_shadows();
-      ctx->make_shadow("T1", ctx->sh_t1);
+      // FP32 copies of the operands large products read in place: the amplitudes at every call
+      // (inside the timed region), the stored blocks once per load; made after the section's
+      // intermediates hold their memory, and only where the device has room
+      auto& ops = ctx->sections.at(sec);
+      if (!ctx->warmed.count(&ops)) {
+        ctx->warm_pool(ops);
+        ctx->warmed.insert(&ops);
+      }
       ctx->make_shadow("T2", ctx->sh_t2);
+      ctx->make_shadow("T1", ctx->sh_t1);
+      ctx->static_shadows();
     }
     ctx->run(ctx->sections.at(sec), term_mask);
     ctx->slots[ctx->slot_of.at("T1")].ptr32 = nullptr;
@@ -1661,6 +1680,7 @@ int ric_energy(ric_ctx* ctx, const double* T1, const double* T2, double* e_corr,
     ctx->Edev.ensure(4);
     ctx->bind("E", ctx->Edev.p);
     ctx->precision = RIC_FP64;
+    ctx->drop_shadows();   // FP64 only: return the mixed path's FP32 operand copies
     HIPCHK(ric::fill(ctx->Edev.p, 1, 0.0, ctx->stream));
     ctx->run(ctx->sections.at("energy"));
     if (e0) {
