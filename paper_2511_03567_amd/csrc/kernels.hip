@@ -51,6 +51,50 @@ strided_axpby(Iter it, double alpha, const TI* __restrict__ in, double beta, TO*
   }
 }
 
+// The same map when the output's stride-1 dimension (da) and the input's (db) differ: a
+// workgroup moves a 32 x 32 tile of (da, db) through LDS, reading rows that are contiguous in
+// the input and writing rows that are contiguous in the output, for one index of the other
+// dimensions at a time (grid.y strides over them; the loop bounds are uniform per workgroup).
+constexpr int kTile = 32;
+
+template <typename TO, typename TI>
+__global__ void __launch_bounds__(256)
+strided_tile(Iter it, int da, int db, double alpha, const TI* __restrict__ in, double beta, TO* __restrict__ out) {
+  __shared__ double tile[kTile][kTile + 1];
+  const long ea = it.ext[da], eb = it.ext[db];
+  const long nta = (ea + kTile - 1) / kTile;
+  const long a0 = (long)(blockIdx.x % nta) * kTile, b0 = (long)(blockIdx.x / nta) * kTile;
+  const int tx = threadIdx.x & (kTile - 1), ty = threadIdx.x / kTile;
+  const long sia = it.si[da], sob = it.so[db];
+  long outer = 1;
+  for (int d = 0; d < it.nd; ++d)
+    if (d != da && d != db) outer *= it.ext[d];
+  for (long o = blockIdx.y; o < outer; o += gridDim.y) {
+    long rem = o, bi = 0, bo = 0;
+    for (int d = it.nd - 1; d >= 0; --d) {
+      if (d == da || d == db) continue;
+      const long e = it.ext[d], x = rem % e;
+      rem /= e;
+      bi += x * it.si[d];
+      bo += x * it.so[d];
+    }
+    for (int j = ty; j < kTile; j += 256 / kTile) {
+      const long a = a0 + j, b = b0 + tx;
+      if (a < ea && b < eb) tile[j][tx] = (double)in[bi + a * sia + b];
+    }
+    __syncthreads();
+    for (int j = ty; j < kTile; j += 256 / kTile) {
+      const long b = b0 + j, a = a0 + tx;
+      if (a < ea && b < eb) {
+        const long oo = bo + a + b * sob;
+        const double v = alpha * tile[tx][j];
+        out[oo] = beta == 0.0 ? (TO)v : (TO)(beta * (double)out[oo] + v);
+      }
+    }
+    __syncthreads();
+  }
+}
+
 __global__ void fill_kernel(double* __restrict__ p, long n, double v) {
   for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) p[t] = v;
 }
@@ -734,6 +778,22 @@ __global__ void ladder_scatter_pm(const double* __restrict__ sp, const double* _
 template <typename TO, typename TI>
 hipError_t launch_strided(const Iter& it, double alpha, const TI* in, double beta, TO* out, hipStream_t st) {
   if (it.total <= 0) return hipSuccess;
+  // a transposing map (the stride-1 dimensions of output and input differ) of some size goes
+  // through LDS tiles; the element-wise kernel reads such an input a stride apart
+  int da = -1, db = -1;
+  for (int d = 0; d < it.nd; ++d) {
+    if (da < 0 && it.so[d] == 1 && it.ext[d] > 1) da = d;
+    if (db < 0 && it.si[d] == 1 && it.ext[d] > 1) db = d;
+  }
+  if (da >= 0 && db >= 0 && da != db && it.ext[da] >= 16 && it.ext[db] >= 16 && it.total >= (1L << 16)) {
+    const long nt = ((it.ext[da] + kTile - 1) / kTile) * ((it.ext[db] + kTile - 1) / kTile);
+    const long outer = it.total / (it.ext[da] * it.ext[db]);
+    if (nt < (1L << 31)) {
+      hipLaunchKernelGGL((strided_tile<TO, TI>), dim3((unsigned)nt, (unsigned)std::min<long>(outer, 65535)), dim3(256), 0,
+                         st, it, da, db, alpha, in, beta, out);
+      return hipGetLastError();
+    }
+  }
   if (it.total < (1L << 32))
     hipLaunchKernelGGL((strided_axpby<TO, TI, unsigned>), dim3(blocks_for(it.total)), dim3(kThreads), 0, st, it,
                        alpha, in, beta, out);
