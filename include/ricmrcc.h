@@ -125,9 +125,12 @@ int ric_load_rdms(ric_ctx* ctx, const double* G1, const double* G2, const double
 /* Many-body residuals (Section 2.2) of the amplitudes T1, T2 (layout above):
  * R1 = r^c_k (alpha), R2 = r^{c dbar}_{k lbar}.  precision: RIC_FP64, or
  * RIC_FP32MIX (large contractions with fp32 MFMA operands and fp64 accumulation;
- * cumulant, energy and update work stays fp64).  term_mask (RIC_TERMS_*): the term groups
- * evaluated, RIC_TERMS_ALL for the residual itself.  R1, R2 are overwritten (the excluded
- * blocks zero, R2 pair-symmetric in every case). */
+ * cumulant, energy and update work stays fp64).  In RIC_FP32MIX the context keeps fp32 copies
+ * of T1, T2, the DF factors and the stored integral blocks (half their size; about 25 GB at 809
+ * orbitals) while at least 16 GB of the device stay free; ric_energy and the adjoint calls
+ * release them.  term_mask (RIC_TERMS_*): the term groups evaluated, RIC_TERMS_ALL for the
+ * residual itself.  R1, R2 are overwritten (the excluded blocks zero, R2 pair-symmetric in
+ * every case). */
 int ric_residual(ric_ctx* ctx, const double* T1, const double* T2, double* R1, double* R2, int precision,
                  unsigned term_mask);
 

@@ -2,7 +2,7 @@
 
 Calls only the oracle and the seeded input generators.  Run from the repository root:
     python tests/golden/make_solve_golden.py            # every case
-    python tests/golden/make_solve_golden.py --diis     # only the DIIS cases, kept beside the others
+    python tests/golden/make_solve_golden.py --diis [name ...]   # (some of) the DIIS cases, merged by name
 
 "cases": the oracle's plain regularized Jacobi iteration (eq. ric-update) from T = 0.
 "diis_cases": the same fixed point reached faster by DIIS over the oracle's update, for shapes
@@ -30,8 +30,9 @@ from oracle import ricmrcc as R  # noqa: E402
 
 CASES = [("tiny_cas44", 0.5), ("tiny_cas44", 0.25)]
 TOL = 1e-10
-# (name, nc, na, nv, naux, seed, s)
-DIIS_CASES = [("cas88_nv40", 10, 8, 40, 120, 2, 0.5)]
+# (name, nc, na, nv, naux, seed, s): the CAS(8,8) active space on 40 virtuals, and the CAS(6,6)
+# workload of the adjoint tests (nc=6, nv=60, naux=180) whole
+DIIS_CASES = [("cas88_nv40", 10, 8, 40, 120, 2, 0.5), ("adjoint_cas66", 6, 6, 60, 180, 3, 0.5)]
 DIIS_TOL = 1e-9
 DIIS_M = 6
 
@@ -73,9 +74,12 @@ def solve_diis(ref, s, tol, m, max_iter=100):
 def main():
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_solve.json")
     if "--diis" in sys.argv:
+        names = sys.argv[sys.argv.index("--diis") + 1:] or [c[0] for c in DIIS_CASES]
         with open(path) as fh:
             doc = json.load(fh)
-        doc["diis_cases"] = run_diis()
+        new = {c["config"]: c for c in run_diis(names)}
+        old = [c for c in doc.get("diis_cases", []) if c["config"] not in new]
+        doc["diis_cases"] = old + list(new.values())
         with open(path, "w") as fh:
             json.dump(doc, fh, indent=1)
         return
@@ -85,9 +89,11 @@ def main():
         json.dump(doc, fh, indent=1)
 
 
-def run_diis():
+def run_diis(names=None):
     out = []
     for name, nc, na, nv, naux, seed, s in DIIS_CASES:
+        if names is not None and name not in names:
+            continue
         cfg = S.custom_config(name, nc, na, nv, naux, seed)
         inp = S.make_inputs(cfg)
         ref = R.Reference(cfg.nc, cfg.na, cfg.nv, inp.f, inp.B, inp.G1, inp.G2, inp.G3)

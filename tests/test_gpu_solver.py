@@ -54,11 +54,11 @@ def test_solve_matches_oracle(case):
 
 
 @pytest.mark.parametrize("case", _golden("diis_cases"), ids=lambda c: f"{c['config']}-s{c['s']}")
-def test_diis_solve_matches_oracle_cas88(case):
-    """The CAS(8,8) active space with the CAS(8,8) workload's core (nc=10) on 40 virtuals
-    (naux=120): converged E_corr against the oracle's own fixed point (DIIS over the oracle's
-    update, make_solve_golden.py --diis): FP64 within 1e-8 E_h, FP32-mixed iterations with FP64
-    polish within 1e-6 E_h."""
+def test_diis_solve_matches_oracle_fixed_point(case):
+    """Converged E_corr against the oracle's own fixed point (DIIS over the oracle's update,
+    make_solve_golden.py --diis): the CAS(8,8) active space with the CAS(8,8) workload's core
+    (nc=10) on 40 virtuals (naux=120), and the CAS(6,6) workload (nc=6, nv=60, naux=180).
+    FP64 within 1e-8 E_h, FP32-mixed iterations with FP64 polish within 1e-6 E_h."""
     from paper_2511_03567_amd import ric
     cfg = S.custom_config(case["config"], case["nc"], case["na"], case["nv"], case["naux"], case["seed"])
     print(f"DIIS solve {case['config']} s={case['s']}", flush=True)
