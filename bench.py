@@ -145,11 +145,11 @@ def ladder_traffic(config):
 
 # shapes (nc, na, nv, naux) the oracle is timed on; nc : nv : naux follow the benchmark's
 # 40 : 757 : 2200 roughly, with a 4-orbital active space
-CPU_SAMPLES = [(2, 4, 16, 40), (3, 4, 24, 60), (4, 4, 32, 80)]
+CPU_SAMPLES = [(2, 4, 16, 40), (3, 4, 24, 60), (4, 4, 32, 80), (5, 4, 40, 100)]
 
 
 def cpu_baseline(cfg):
-    """The oracle timed on a bounded sample: its residual + update at three small shapes,
+    """The oracle timed on a bounded sample: its residual + update at four small shapes,
     a power law t = a N^b fitted in the ladder's size measure N = nH^2 nP^4, extrapolated to
     the benchmark shape (labelled as such)."""
     import numpy as np
@@ -197,7 +197,7 @@ def cpu_baseline(cfg):
         "kind": "oracle",
         "sample": ("oracle residual + update timed at (nc, na, nv, naux) = "
                    + ", ".join(f"({s['nc']},{s['na']},{s['nv']},{s['naux']}): {s['s']} s" for s in samples)
-                   + f" on {model}; power law t = a N^b in N = nH^2 nP^4 fitted over the three (b = {b:.3f}), "
+                   + f" on {model}; power law t = a N^b in N = nH^2 nP^4 fitted over the four (b = {b:.3f}), "
                      f"extrapolated to N = {n_full:.3e} at the benchmark shape"),
         "fit_exponent": float(b),
         "samples": samples,

@@ -22,7 +22,6 @@ struct Iter {
 
 hipError_t strided_copy(const Iter& it, double alpha, const double* in, double beta, double* out, hipStream_t st);
 hipError_t strided_copy_f32(const Iter& it, double alpha, const double* in, float* out, hipStream_t st);
-hipError_t strided_copy_f32f32(const Iter& it, const float* in, float* out, hipStream_t st);
 hipError_t fill(double* p, long n, double v, hipStream_t st);
 hipError_t symmetrize_pairs(double* x, int nh, int np, hipStream_t st);
 hipError_t mask_active(double* r1, double* r2, int nc, int na, int nv, hipStream_t st);

@@ -811,10 +811,6 @@ hipError_t strided_copy_f32(const Iter& it, double alpha, const double* in, floa
   return launch_strided<float, double>(it, alpha, in, 0.0, out, st);
 }
 
-hipError_t strided_copy_f32f32(const Iter& it, const float* in, float* out, hipStream_t st) {
-  return launch_strided<float, float>(it, 1.0, in, 0.0, out, st);
-}
-
 hipError_t fill(double* p, long n, double v, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(fill_kernel, dim3(blocks_for(n)), dim3(kThreads), 0, st, p, n, v);
