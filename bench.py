@@ -42,7 +42,7 @@ METRIC = "s/residual-iteration & TFLOP/s, 809-orb CAS(12,12); FP32-mixed vs FP64
 # operand pre-combination), so that TFLOP/s against it follows s/iteration as the plan changes
 FIXED_FLOPS = {"b12_cas1212": 4.397209499209308e15}
 
-LADDER_TRAFFIC = {"bytes": 7.1095e+13, "sources_sha256": "245d76b56e7d3d2a", "workload": "b12_cas1212"}
+LADDER_TRAFFIC = {"bytes": 7.1152e+13, "sources_sha256": "08543e8f6f8399d3", "workload": "b12_cas1212"}
 
 
 def log(msg):

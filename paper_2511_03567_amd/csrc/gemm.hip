@@ -20,8 +20,10 @@
 //
 // FP64 path: v_mfma_f64_16x16x4f64 (16x16 tile, 4-deep K step).
 // FP32 path (mixed precision): v_mfma_f32_16x16x4f32 on fp32 operands; the
-// fp32 tile accumulators are flushed into fp64 accumulators every slab so the
-// long K sums of the residual are carried in fp64.
+// fp32 tile accumulators are flushed into fp64 accumulators every 128 terms of K
+// (every fourth 32-deep slab, and at the end of the tile's K range) so the long K
+// sums of the residual are carried in fp64.  Flushing every slab instead costs
+// 6-7 % of the fp32 GEMM rate on gfx950 (the fp64 adds and conversions).
 //
 // Lane layout of the 16x16x4 MFMAs (64 lanes, measured on gfx950): operand A
 // element (i, k) sits in lane i + 16 k, operand B element (k, j) in lane j + 16 k.
@@ -243,6 +245,8 @@ gemm_nt_kernel(int M, int N, int K, double alpha, const T* __restrict__ A, long 
 
   T va[TileA::E], vb[TileB::E];
   int buf = 0;
+  constexpr int kCarrySlabs = kMixed ? (BK < 128 ? 128 / BK : 1) : 1;
+  int ncarry = 0;
   if (kbeg < kend) {
     TileA::template fetch<VEC>(A, lda, M, kend, m0, kbeg, tid, va);
     TileB::template fetch<VEC>(B, ldb, N, kend, n0, kbeg, tid, vb);
@@ -273,15 +277,18 @@ gemm_nt_kernel(int M, int N, int K, double alpha, const T* __restrict__ A, long 
         for (int j = 0; j < TJ; ++j) mma(acc[i][j], av[i], bv[j]);
     }
     if constexpr (kMixed) {
-      // carry the slab's fp32 partial sums in fp64
+      // carry the fp32 partial sums of the last kCarrySlabs slabs in fp64
+      if (++ncarry == kCarrySlabs || !more) {
+        ncarry = 0;
 #pragma unroll
-      for (int i = 0; i < TI; ++i)
+        for (int i = 0; i < TI; ++i)
 #pragma unroll
-        for (int j = 0; j < TJ; ++j) {
+          for (int j = 0; j < TJ; ++j) {
 #pragma unroll
-          for (int r = 0; r < 4; ++r) acc64[i][j][r] += (double)acc[i][j][r];
-          acc[i][j] = Acc{0, 0, 0, 0};
-        }
+            for (int r = 0; r < 4; ++r) acc64[i][j][r] += (double)acc[i][j][r];
+            acc[i][j] = Acc{0, 0, 0, 0};
+          }
+      }
     }
     if (more) {
       TileA::stash(As[buf ^ 1], tid, va);
