@@ -39,6 +39,17 @@
  * Errors: functions return RIC_OK (0) or a negative code; the message of the
  * last error is available from ric_last_error().  No C++ exception crosses
  * the ABI.  There is no CPU fallback: every step runs in the library's HIP kernels.
+ *
+ * Environment (tuning and diagnostics; none changes what is computed beyond rounding):
+ *   RIC_LADDER_BUDGET   elements of the ladder's (ce|df) block built per chunk of c rows
+ *                       (default 2.8e9 for the residual, 1.4e9 in the adjoint); read per call
+ *   RIC_LOOP_BUDGET     elements per chunk of a chunked plan intermediate (default 1.5e9)
+ *   RIC_PAD_MIN_FLOPS   products above this many flops get K padded to the vector width (1e10)
+ *   RIC_FP32_MIN_FLOPS  in RIC_FP32MIX, products above this many flops take fp32 operands (1e10)
+ *   RIC_PROFILE         1: device time per operation kind (synchronizes after every operation);
+ *                       2: also each operation above 20 ms
+ *   RIC_PROGRESS        set: one stderr line when each expensive phase of a plan section ends
+ * All but RIC_LADDER_BUDGET are read once, at ric_create.
  */
 #ifndef RICMRCC_H
 #define RICMRCC_H
