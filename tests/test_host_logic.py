@@ -1,4 +1,4 @@
-"""Host-side logic that needs no GPU: the benchmark's flop count and the DIIS extrapolation."""
+"""Host-side logic that needs no GPU: the benchmark's flop count, argument checks and traffic gate, and the DIIS extrapolation."""
 import math
 import os
 import sys
@@ -120,3 +120,32 @@ def test_sorted_tuple_rdms_equal_ordered_tuple_rdms():
         d, c = S.random_ci(rng, na, frac)
         for a, b in zip(S.spinfree_rdms(d, c, na, 3), S.spinfree_rdms_ordered(d, c, na, 3)):
             assert np.abs(a - b).max() < 1e-14
+
+
+def test_bench_refuses_several_gpus_and_bad_step_counts():
+    """bench.py runs on one GPU: --gpus N > 1 and empty step counts exit with a message before any
+    device work."""
+    import subprocess
+    for argv, word in ((["--gpus", "2"], "one GPU"), (["--steps", "0"], "--steps")):
+        p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py")] + argv, capture_output=True,
+                           text=True, timeout=120, cwd=ROOT)
+        assert p.returncode == 2, (argv, p.stderr)
+        assert word in p.stderr
+        assert p.stdout == ""
+
+
+def test_bench_reports_ladder_traffic_only_for_the_counted_state(monkeypatch):
+    """The ladder's HBM bytes come from counter passes on one state of the kernel sources: the line
+    carries them only for that workload and while gemm.hip, kernels.hip and runtime.hip hash to it."""
+    import hashlib
+    import bench
+    h = hashlib.sha256()
+    for f in ("gemm.hip", "kernels.hip", "runtime.hip"):
+        with open(os.path.join(ROOT, "paper_2511_03567_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    state = dict(bench.LADDER_TRAFFIC, sources_sha256=h.hexdigest()[:16])
+    monkeypatch.setattr(bench, "LADDER_TRAFFIC", state)
+    assert bench.ladder_traffic(state["workload"]) == state["bytes"]
+    assert bench.ladder_traffic("mixed_cas88") is None
+    monkeypatch.setattr(bench, "LADDER_TRAFFIC", dict(state, sources_sha256="0" * 16))
+    assert bench.ladder_traffic(state["workload"]) is None
